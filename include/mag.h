@@ -1,0 +1,302 @@
+/*
+ * mag.h -- multiple-Arnoldi Green's-function engine for MI355X (gfx950).
+ *
+ * C ABI of libmag.so.  The library computes, column by column, the Green's
+ * function G = (zS - H)^-1 of a sparse real-symmetric tight-binding pencil
+ * (H, S), S positive definite, in the LCAO basis (the generalized shifted
+ * linear equation, Eq. 1 of arXiv:1210.1531), by one Krylov subspace per
+ * column j over the local cluster of j's atom ("multiple Arnoldi" method,
+ * parallel over j).  From the Ritz data it forms the Fermi-Dirac density
+ * matrix rho (Eq. 2), the chemical potential mu by bisection between the two
+ * Green's-function passes of the memory-saving workflow (Eq. 3), the band and
+ * free energy, their derivatives dA/dH = rho and dA/dS = -pi (pi = energy
+ * density matrix) and, through Slater-Koster derivatives, atomic forces.
+ *
+ * Conventions shared by every entry point
+ *   - Status: MAG_OK (0) or a negative mag_status; mag_last_error() returns a
+ *     message for the last failing call on that context.  No C++ exception
+ *     crosses the ABI.  Output buffers are unspecified after an error.
+ *   - mem_kind: MAG_HOST means the caller's pointers are host memory,
+ *     MAG_DEVICE means device memory on the context's device.  Inputs are
+ *     copied during the call (they need to stay valid only until it returns);
+ *     outputs go to caller-allocated buffers of the documented size.
+ *   - Work is queued on the context's stream; every entry point returns after
+ *     its outputs (device or host) are complete.
+ *   - One context is not thread-safe; distinct contexts are independent.
+ *   - Units: energies eV, lengths Angstrom, forces eV/Angstrom.
+ *   - Basis: every atom carries MAG_NORB = 4 orbitals (s, px, py, pz); basis
+ *     index i = 4 I + alpha for atom I and orbital alpha (the (I, alpha)
+ *     decomposition of the COHP paragraph); M = 4 N.
+ *   - CSR layout of H, S, rho, pi ("block-complete"): row r = (J, alpha)
+ *     lists, for every atom K of the block row of J in ascending order, the
+ *     four columns 4K .. 4K+3; the block rows of the four rows of an atom are
+ *     identical and include J itself.  Entry p of row r, column c of the
+ *     density outputs holds rho_{c r} as obtained from column r, i.e. the
+ *     coefficient of H_{r c} in E_band = sum_r sum_c H_{r c} rho_{c r}.
+ */
+#ifndef MAG_H
+#define MAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAG_NORB 4
+#define MAG_NU_MAX 48       /* largest Krylov dimension */
+#define MAG_CLUSTER_MAX 192 /* largest cluster, atoms (768 orbitals) */
+#define MAG_BLOCKS_MAX 32   /* largest block row (atoms within r_cut, self included) */
+
+typedef struct mag_ctx mag_ctx;
+
+enum mag_status {
+  MAG_OK = 0,
+  MAG_EINVAL = -1,      /* bad argument, size or layout */
+  MAG_ENOMEM = -2,      /* device allocation failed */
+  MAG_EHIP = -3,        /* HIP runtime error */
+  MAG_ENOTPD = -4,      /* a projected overlap s = V^T S V is not positive definite */
+  MAG_EBRACKET = -5,    /* n_electrons outside (0, 2M) or no sign change in the bracket */
+  MAG_ESTATE = -6,      /* call out of order (e.g. density before solve) */
+  MAG_ENONFINITE = -7,  /* NaN or Inf in the input or in an intermediate result */
+  MAG_EUNSUPPORTED = -8 /* size beyond a documented limit */
+};
+
+enum mag_mem { MAG_HOST = 0, MAG_DEVICE = 1 };
+
+/* Memory workflow of Eq. 3.  RECOMPUTE: pass 1 keeps only the spectral data
+ * (eps, w) needed for mu and recomputes every Krylov column for rho in pass 2
+ * (the letter's memory-saving workflow).  STORE: pass 1 also keeps Y d on the
+ * pattern (n_pat x nu doubles per column) and pass 2 reads it back. */
+enum mag_workflow { MAG_WORKFLOW_RECOMPUTE = 0, MAG_WORKFLOW_STORE = 1 };
+
+/* Launch schedule of the per-column Krylov kernels.  PERSISTENT: one launch of
+ * resident workgroups pulling columns (largest clusters first) from a device
+ * queue.  GRID: one launch, one workgroup per column.  PLAIN: one launch per
+ * column.  AUTO: the library's tuned choice.  Per-column results are
+ * bitwise identical across schedules. */
+enum mag_schedule {
+  MAG_SCHED_AUTO = 0,
+  MAG_SCHED_PERSISTENT = 1,
+  MAG_SCHED_GRID = 2,
+  MAG_SCHED_PLAIN = 3
+};
+
+/* ---------------------------------------------------------------------- */
+/* context                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to
+ * enqueue on, or NULL to let the context create its own (default priority).
+ * Errors: MAG_EINVAL (out == NULL, bad device), MAG_EHIP. */
+int mag_create(mag_ctx** out, int device, void* hip_stream);
+
+/* Free every device buffer of the context (no-op on NULL). */
+void mag_destroy(mag_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none); valid until the next
+ * call on ctx.  Never NULL. */
+const char* mag_last_error(const mag_ctx* ctx);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int mag_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* A0: Slater-Koster two-center sp model (the tight-binding form of H, S)   */
+/* ---------------------------------------------------------------------- */
+
+/* Two-center model.  For atoms I, K with d = R_K - R_I, r = |d|, direction
+ * cosines l = d / r and radial factor u(r) = (r0/r)^2 fc(r),
+ * fc = 1 - (10 t^3 - 15 t^4 + 6 t^5), t = clip((r - r_on)/(r_cut - r_on)):
+ *   block_ss = V_ss u, block_s,a = l_a V_sp u, block_a,s = -l_a V_sp u,
+ *   block_a,b = (l_a l_b V_pps + (delta_ab - l_a l_b) V_ppp) u
+ * with (V_ss, V_sp, V_pps, V_ppp) = the v_* fields for H and the s_* fields
+ * for S - I.  Onsite: H = diag(es, ep, ep, ep), S = I.  Pattern: atom pairs
+ * closer than r_cut (minimum image in the orthorhombic box) plus each atom
+ * with itself.  Requires 2 r_cut < every box length. */
+typedef struct {
+  double es, ep;
+  double v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi;
+  double s_ss_sigma, s_sp_sigma, s_pp_sigma, s_pp_pi;
+  double r0, r_on, r_cut;
+} mag_sk_model;
+
+/* Build pattern and values of H and S from positions on the device.
+ * pos: n_atoms x 3 doubles (mem_kind); cell: 3 box lengths (host).
+ * On success *nnz_out = number of CSR nonzeros; fetch the CSR with
+ * mag_sk_get_csr.  Errors: MAG_EINVAL (sizes, 2 r_cut >= box, more than
+ * MAG_BLOCKS_MAX atoms in a block row), MAG_ENONFINITE, MAG_ENOMEM. */
+int mag_sk_build(mag_ctx* ctx, const mag_sk_model* model, int64_t n_atoms,
+                 const double* pos, const double cell[3], int mem_kind,
+                 int64_t* nnz_out);
+
+/* Copy the CSR built by the last mag_sk_build: rowptr (M+1), colind (nnz),
+ * H (nnz), S (nnz).  Any pointer may be NULL to skip it.  MAG_ESTATE if no
+ * build was done. */
+int mag_sk_get_csr(mag_ctx* ctx, int64_t* rowptr, int32_t* colind, double* H,
+                   double* S, int mem_kind);
+
+/* Recompute H and S values on the pattern of the last build for new
+ * positions pos (n_atoms x 3); the pattern is kept even if atoms cross
+ * r_cut (the smooth cutoff makes such entries vanish there). */
+int mag_sk_values(mag_ctx* ctx, const double* pos, double* H, double* S,
+                  int mem_kind);
+
+/* Vector-Jacobian product of the SK map on the built pattern:
+ * grad[I] = sum_p gH[p] dH_p/dR_I + gS[p] dS_p/dR_I  (n_atoms x 3). */
+int mag_sk_vjp(mag_ctx* ctx, const double* pos, const double* gH,
+               const double* gS, double* grad, int mem_kind);
+
+/* ---------------------------------------------------------------------- */
+/* system (H, S, clusters)                                                  */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  int64_t n_atoms;           /* N */
+  int64_t nnz;               /* CSR nonzeros */
+  const int64_t* rowptr;     /* M + 1, block-complete layout (see top) */
+  const int32_t* colind;     /* nnz */
+  const double* H;           /* nnz, eV */
+  const double* S;           /* nnz */
+  const double* pos;         /* N x 3, needed when clusters are built here and for forces */
+  double cell[3];            /* orthorhombic box lengths */
+  double r_cluster;          /* cluster radius; <= 0, or 2 r >= min box length: whole cell */
+  const int64_t* clus_ptr;   /* N + 1, or NULL to build clusters from pos */
+  const int32_t* clus_atoms; /* ascending atom ids of each cluster, or NULL */
+} mag_system;
+
+/* Set the pencil and the clusters.  The cluster of atom J (a reading of the
+ * letter's column-parallel generation of G) holds every atom I with
+ * |R_I - R_J| <= r_cluster (minimum image, inclusive), J included, with all
+ * four orbitals, ordered by atom id then orbital.  Every atom of J's block row
+ * must lie in J's cluster.  Errors: MAG_EINVAL (layout not block-complete,
+ * sizes), MAG_EUNSUPPORTED (cluster larger than MAG_CLUSTER_MAX atoms),
+ * MAG_ENONFINITE, MAG_ENOMEM. */
+int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind);
+
+/* Replace the values of H and S (same pattern, nnz each). */
+int mag_update_values(mag_ctx* ctx, const double* H, const double* S, int mem_kind);
+
+/* Copy the clusters in use: clus_ptr (N+1) and clus_atoms (clus_ptr[N]).
+ * Either pointer may be NULL; *total_out (may be NULL) receives clus_ptr[N]. */
+int mag_get_clusters(mag_ctx* ctx, int64_t* clus_ptr, int32_t* clus_atoms,
+                     int64_t* total_out, int mem_kind);
+
+/* ---------------------------------------------------------------------- */
+/* forward: Krylov columns, mu, energy                                      */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  int nu;             /* Krylov dimension, 1 .. MAG_NU_MAX (clamped per column to 4|C|) */
+  double kT;          /* Fermi-Dirac temperature, eV, > 0 */
+  double n_electrons; /* electron count, 0 < n_electrons < 2 M (spin factor 2) */
+  double mu_tol;      /* bisection stops when the bracket is <= mu_tol (<= 0: 1e-12 eV) */
+  double mu_fixed;    /* NaN: find mu by bisection; else use this mu */
+  double breakdown;   /* Krylov breakdown threshold, relative (<= 0: 1e-12) */
+  int workflow;       /* mag_workflow */
+  int schedule;       /* mag_schedule */
+} mag_opts;
+
+/* Fill opts with the defaults (nu 30, kT 0.1, n_electrons 0 (must be set),
+ * mu_tol 1e-12, mu_fixed NaN, breakdown 1e-12, RECOMPUTE, AUTO). */
+void mag_opts_default(mag_opts* opts);
+
+/* Pass 1 of Eq. 3 over every column, then mu, then the energies.
+ * Per column j = (J, alpha), with l the local index of j in J's cluster C:
+ * the Krylov space K_nu(H_C; e_l) (grown by SpMV and re-orthogonalized
+ * Gram-Schmidt; the basis is Euclidean-orthonormal, which spans the same
+ * space as the S-orthonormal basis of the reading), the projected pencil
+ * (h, s) = (Q^T H_C Q, Q^T S_C Q), its eigenpairs h c = eps s c, and the
+ * weights w_k = 2 d_k g_k with d = (Qc)^T e_l, g = (Qc)^T S_C e_l.
+ * mu solves N(mu) = sum_jk w_jk f((eps_jk - mu)/kT) = n_electrons by
+ * bisection (mid = lo + (hi - lo)/2 on [min eps - 40 kT, max eps + 40 kT]).
+ * E_band = sum w f eps, A_free = E_band - kT sum w s(f).  Any output pointer
+ * may be NULL.  Errors: MAG_ESTATE (no system), MAG_EINVAL (opts),
+ * MAG_EBRACKET, MAG_ENOTPD, MAG_ENONFINITE. */
+int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu,
+                      double* E_band, double* A_free);
+
+/* Spectral data of the last solve: eps, w (M x nu, row j = column j, entries
+ * k >= nu_eff[j] are 0) and nu_eff (M).  Any pointer may be NULL. */
+int mag_spectra(mag_ctx* ctx, double* eps, double* w, int32_t* nu_eff, int mem_kind);
+
+/* Energies of the last solve: E_band, A_free (Mermin free energy), the
+ * electron count N = sum w f and the entropy sum S_ent = sum w s(f).  Any
+ * pointer may be NULL. */
+int mag_energy(mag_ctx* ctx, double* E_band, double* A_free, double* N_check,
+               double* S_ent);
+
+/* Ritz data of selected columns at the current system and opts (no mu, no
+ * state change): eps, w (n x nu), nu_eff (n).  For sampled checks at any
+ * size.  cols: n global column ids (mem_kind). */
+int mag_column_spectra(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols,
+                       int64_t n, double* eps, double* w, int32_t* nu_eff,
+                       int mem_kind);
+
+/* ---------------------------------------------------------------------- */
+/* pass 2: density matrix, Green's function columns                         */
+/* ---------------------------------------------------------------------- */
+
+/* rho and pi = energy-density matrix on the CSR pattern of H (nnz each):
+ *   rho_ij = 2 sum_k f_k Y_ik d_k,  pi_ij = 2 sum_k f_k eps_k Y_ik d_k,
+ * Y = Q c, for i in the block row of j's atom (Eq. 2 on the Ritz spectrum).
+ * Runs pass 2 of the last solve's workflow.  pi may be NULL. */
+int mag_density_matrix(mag_ctx* ctx, double* rho_csr, double* pi_csr, int mem_kind);
+
+/* Full cluster columns of rho at the last solve's mu: for column cols[i] the
+ * values rho_{c j} for every orbital c of its cluster in cluster order are
+ * written at rho_out[offsets[i] .. offsets[i+1]), offsets[i+1] - offsets[i] =
+ * 4 |C(atom of cols[i])|.  offsets (n+1, int64, host) is filled by the call;
+ * pass rho_out = NULL to get the offsets only. */
+int mag_cluster_columns(mag_ctx* ctx, const int32_t* cols, int64_t n,
+                        double* rho_out, int64_t* offsets, int mem_kind);
+
+/* Galerkin Green's-function columns G_{c j}(z) = sum_k Y_ck d_k / (z - eps_k)
+ * (no spin factor) at nz complex energies z (re, im pairs, host), for every
+ * orbital c of the cluster; output complex (re, im) at
+ * G_out[2 (offsets[i] * nz + q * len_i + c)] for column i, energy q, local
+ * orbital c, with offsets as in mag_cluster_columns. */
+int mag_green_columns(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols,
+                      int64_t n, const double* z, int nz, double* G_out,
+                      int64_t* offsets, int mem_kind);
+
+/* ---------------------------------------------------------------------- */
+/* derivatives                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Adjoint of A_free: dA/dH = gA * rho and dA/dS = -gA * pi on the CSR
+ * pattern (nnz each; either may be NULL).  Runs pass 2 if needed. */
+int mag_backward(mag_ctx* ctx, double gA, double* dAdH_csr, double* dAdS_csr,
+                 int mem_kind);
+
+/* Forces F_I = -sum_p [rho_p dH_p/dR_I - pi_p dS_p/dR_I] (n_atoms x 3) from
+ * the density matrices of the last solve and the SK derivatives of `model`
+ * at the system's positions.  Requires mag_system.pos and a pattern in the
+ * layout of mag_sk_build. */
+int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind);
+
+/* ---------------------------------------------------------------------- */
+/* diagnostics                                                              */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  double t_set_system_ms;  /* last mag_set_system */
+  double t_pass1_ms;       /* last pass 1 (Krylov + projected eigensolve) */
+  double t_mu_ms;          /* last bisection + energy */
+  double t_pass2_ms;       /* last pass 2 */
+  double t_forces_ms;      /* last mag_forces */
+  int64_t n_columns;       /* M */
+  int64_t max_cluster;     /* largest cluster, orbitals */
+  int64_t sum_cluster_nnz; /* sum over atoms of nonzeros of H_C */
+  int64_t device_bytes;    /* device memory held by the context */
+  int32_t bisect_levels;   /* halvings of the last bisection */
+  int32_t schedule_used;   /* mag_schedule actually launched */
+} mag_stats;
+
+int mag_get_stats(mag_ctx* ctx, mag_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAG_H */

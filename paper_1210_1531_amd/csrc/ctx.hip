@@ -1,0 +1,1146 @@
+// Host side of the C ABI declared in include/mag.h: context, system set-up,
+// the two Green's-function passes of the memory-saving workflow (Eq. 3), the
+// chemical potential, energies, derivatives and forces.
+#include <algorithm>
+#include <cstdio>
+#include <numeric>
+
+#include "mag_internal.h"
+
+using namespace mag;
+
+namespace {
+
+int fail(mag_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, MAG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define ALLOC(buf, bytes)                                                                  \
+  do {                                                                                     \
+    if ((buf).reserve(bytes) != hipSuccess) {                                              \
+      (void)hipGetLastError();                                                             \
+      return fail(ctx, MAG_ENOMEM, std::string("device allocation of ") +                 \
+                                       std::to_string((size_t)(bytes)) + " bytes failed"); \
+    }                                                                                      \
+  } while (0)
+
+#define TRY(expr)                \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != MAG_OK) return rc_; \
+  } while (0)
+
+hipMemcpyKind kind_in(int mem_kind) {
+  return mem_kind == MAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_out(int mem_kind) {
+  return mem_kind == MAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+int check_mem_kind(mag_ctx* ctx, int mem_kind) {
+  if (mem_kind != MAG_HOST && mem_kind != MAG_DEVICE)
+    return fail(ctx, MAG_EINVAL, "mem_kind must be MAG_HOST or MAG_DEVICE");
+  return MAG_OK;
+}
+
+int copy_in(mag_ctx* ctx, DevBuf& dst, const void* src, size_t bytes, int mem_kind) {
+  ALLOC(dst, bytes);
+  if (bytes) HIPCHK(hipMemcpyAsync(dst.p, src, bytes, kind_in(mem_kind), ctx->stream));
+  return MAG_OK;
+}
+
+int copy_out(mag_ctx* ctx, void* dst, const void* src, size_t bytes, int mem_kind) {
+  if (!dst || !bytes) return MAG_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, kind_out(mem_kind), ctx->stream));
+  return MAG_OK;
+}
+
+int sync(mag_ctx* ctx) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return MAG_OK;
+}
+
+// read and clear the kernel error flags; map them to a status
+int take_errors(mag_ctx* ctx, const char* where) {
+  int32_t flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, ctx->errflag.p, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!flags) return MAG_OK;
+  HIPCHK(hipMemsetAsync(ctx->errflag.p, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::string w(where);
+  if (flags & KERR_NONFINITE) return fail(ctx, MAG_ENONFINITE, w + ": non-finite value");
+  if (flags & KERR_NOTPD)
+    return fail(ctx, MAG_ENOTPD, w + ": projected overlap not positive definite");
+  if (flags & KERR_LAYOUT)
+    return fail(ctx, MAG_EINVAL, w + ": CSR pattern is not block-complete and symmetric");
+  if (flags & KERR_PATTERN)
+    return fail(ctx, MAG_EINVAL, w + ": a block-row atom lies outside the column's cluster");
+  if (flags & KERR_CAPACITY)
+    return fail(ctx, MAG_EUNSUPPORTED, w + ": a cluster or block row exceeds the library limits");
+  return fail(ctx, MAG_EHIP, w + ": kernel error flag " + std::to_string(flags));
+}
+
+SKModelDev to_dev(const mag_sk_model& m) {
+  SKModelDev d;
+  d.es = m.es;
+  d.ep = m.ep;
+  d.vh[0] = m.v_ss_sigma;
+  d.vh[1] = m.v_sp_sigma;
+  d.vh[2] = m.v_pp_sigma;
+  d.vh[3] = m.v_pp_pi;
+  d.vs[0] = m.s_ss_sigma;
+  d.vs[1] = m.s_sp_sigma;
+  d.vs[2] = m.s_pp_sigma;
+  d.vs[3] = m.s_pp_pi;
+  d.r0 = m.r0;
+  d.r_on = m.r_on;
+  d.r_cut = m.r_cut;
+  return d;
+}
+
+bool model_ok(const mag_sk_model* m) {
+  if (!m) return false;
+  const double v[] = {m->es, m->ep, m->v_ss_sigma, m->v_sp_sigma, m->v_pp_sigma, m->v_pp_pi,
+                      m->s_ss_sigma, m->s_sp_sigma, m->s_pp_sigma, m->s_pp_pi, m->r0, m->r_on,
+                      m->r_cut};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return m->r0 > 0.0 && m->r_on > 0.0 && m->r_cut > m->r_on;
+}
+
+int device_count_cus(int device) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 256;
+  return n > 0 ? n : 256;
+}
+
+bool whole_cell(const double cell[3], double rc) {
+  const double lmin = std::min(cell[0], std::min(cell[1], cell[2]));
+  return rc <= 0.0 || 2.0 * rc >= lmin;
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s);
+  }
+  double stop_ms() {
+    float ms = 0.f;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// running the per-column kernels over a list of columns
+// ---------------------------------------------------------------------------
+struct ColumnJob {
+  const int32_t* cols_dev = nullptr;  // device column list (slot order)
+  std::vector<int32_t> cols_host;     // same, host copy
+  int nu = 30;
+  double breakdown = 1e-12;
+  int schedule = MAG_SCHED_AUTO;
+  int full = 0;            // write every cluster row of Q
+  // eig outputs
+  double* eps = nullptr;   // spectra rows (by column id or by slot)
+  double* w = nullptr;
+  int32_t* nu_eff = nullptr;
+  int out_by_slot = 0;
+  // P and what to do with it
+  int want_P = 0;          // compute P = Y d on the rows
+  double* P_store = nullptr;  // if set: P goes to this array with base rowptr[j] (pmode 1)
+  // per-chunk consumer after the eig kernel
+  int consumer = 0;        // 0 none, 1 density on pattern, 2 cluster rho, 3 Green's columns
+  double* rho = nullptr;
+  double* pi = nullptr;
+  const int64_t* out_off = nullptr;  // consumers 2, 3: output offsets by slot (device)
+  double* out = nullptr;
+  const double* z = nullptr;         // consumer 3: complex energies (device)
+  int nz = 0;
+};
+
+int rows_class(int atoms) {
+  const int nC = NORB * atoms;
+  const int t = krylov_threads();
+  return (nC + t - 1) / t;
+}
+
+int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr) {
+  (void)slot_done_hook;
+  const int64_t n = (int64_t)job.cols_host.size();
+  if (n == 0) return MAG_OK;
+  const int cap = krylov_capacity(job.nu);
+  const int pat_stride = job.full ? NC_MAX : PAT_MAX;
+  const size_t per_slot =
+      sizeof(double) * ((size_t)2 * cap * cap + cap + (size_t)pat_stride * cap) + 2 * sizeof(int32_t) +
+      (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0);
+  const char* env = std::getenv("MAG_SCRATCH_GB");
+  const double budget_gb = env ? std::atof(env) : 8.0;
+  int64_t bmax = (int64_t)(budget_gb * 1e9 / (double)per_slot);
+  if (bmax < 1) bmax = 1;
+  const int64_t bsz = std::min(n, bmax);
+  ALLOC(ctx->k_hs, sizeof(double) * bsz * 2 * cap * cap);
+  ALLOC(ctx->k_urow, sizeof(double) * bsz * cap);
+  ALLOC(ctx->k_qpat, sizeof(double) * bsz * (size_t)pat_stride * cap);
+  ALLOC(ctx->k_nu, sizeof(int32_t) * bsz);
+  ALLOC(ctx->k_npat, sizeof(int32_t) * bsz);
+  ALLOC(ctx->k_queue, sizeof(int32_t) * 4);
+  double* Pbuf = job.P_store;
+  if (job.want_P && !job.P_store) {
+    ALLOC(ctx->tmp_out, sizeof(double) * bsz * (size_t)pat_stride * job.nu);
+    Pbuf = ctx->tmp_out.as<double>();
+  }
+  const int ncu = device_count_cus(ctx->device);
+  int schedule = job.schedule == MAG_SCHED_AUTO ? MAG_SCHED_PERSISTENT : job.schedule;
+  ctx->stats.schedule_used = schedule;
+
+  int64_t i0 = 0;
+  while (i0 < n) {
+    // chunk: same rows-per-thread class, at most bsz slots
+    const int J0 = job.cols_host[i0] >> 2;
+    const int cls = rows_class(ctx->h_clus_size[J0]);
+    int64_t i1 = i0 + 1;
+    while (i1 < n && i1 - i0 < bsz && rows_class(ctx->h_clus_size[job.cols_host[i1] >> 2]) == cls)
+      ++i1;
+    const int64_t cnt = i1 - i0;
+    if (cls > 3) return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the kernel supports");
+
+    KrylovArgs ka{};
+    ka.bptr = ctx->bptr.as<int32_t>();
+    ka.bcol = ctx->bcol.as<int32_t>();
+    ka.bval = ctx->bval.as<double>();
+    ka.clus_ptr = ctx->clus_ptr.as<int64_t>();
+    ka.clus_atoms = ctx->clus_atoms.as<int32_t>();
+    ka.cols = job.cols_dev + i0;
+    ka.ncols = cnt;
+    ka.queue = nullptr;
+    ka.nu = job.nu;
+    ka.breakdown = job.breakdown;
+    ka.hs = ctx->k_hs.as<double>();
+    ka.urow = ctx->k_urow.as<double>();
+    ka.qpat = ctx->k_qpat.as<double>();
+    ka.nu_eff = ctx->k_nu.as<int32_t>();
+    ka.npat = ctx->k_npat.as<int32_t>();
+    ka.err = ctx->errflag.as<int32_t>();
+    ka.cap = cap;
+    ka.pat_stride = pat_stride;
+    ka.full = job.full;
+
+    EigArgs ea{};
+    ea.hs = ka.hs;
+    ea.urow = ka.urow;
+    ea.qpat = ka.qpat;
+    ea.nu_eff_in = ka.nu_eff;
+    ea.cols = ka.cols;
+    ea.rowptr = ctx->rowptr.as<int64_t>();
+    ea.ncols = cnt;
+    ea.cap = cap;
+    ea.nu = job.nu;
+    ea.eps = job.out_by_slot ? job.eps + i0 * job.nu : job.eps;
+    ea.w = job.out_by_slot ? job.w + i0 * job.nu : job.w;
+    ea.nu_eff_out = job.out_by_slot ? job.nu_eff + i0 : job.nu_eff;
+    ea.npat = ka.npat;
+    ea.P = job.want_P ? Pbuf : nullptr;
+    ea.pmode = job.P_store ? 1 : 0;
+    ea.pat_stride = pat_stride;
+    ea.out_by_slot = job.out_by_slot;
+    ea.err = ka.err;
+
+    if (schedule == MAG_SCHED_PLAIN) {
+      for (int64_t q = 0; q < cnt; ++q) {
+        KrylovArgs k1 = ka;
+        k1.cols = ka.cols + q;
+        k1.ncols = 1;
+        k1.hs = ka.hs + q * 2 * cap * cap;
+        k1.urow = ka.urow + q * cap;
+        k1.qpat = ka.qpat + q * (int64_t)pat_stride * cap;
+        k1.nu_eff = ka.nu_eff + q;
+        k1.npat = ka.npat + q;
+        HIPCHK(launch_krylov(k1, cap, cls, 1, ctx->stream));
+        EigArgs e1 = ea;
+        e1.hs = k1.hs;
+        e1.urow = k1.urow;
+        e1.qpat = k1.qpat;
+        e1.nu_eff_in = k1.nu_eff;
+        e1.cols = k1.cols;
+        e1.ncols = 1;
+        e1.npat = k1.npat;
+        if (job.out_by_slot) {
+          e1.eps = ea.eps + q * job.nu;
+          e1.w = ea.w + q * job.nu;
+          e1.nu_eff_out = ea.nu_eff_out + q;
+        }
+        if (e1.P && !job.P_store) e1.P = Pbuf + q * (int64_t)pat_stride * job.nu;
+        HIPCHK(launch_eig(e1, ctx->stream));
+      }
+    } else {
+      int grid = (int)cnt;
+      if (schedule == MAG_SCHED_PERSISTENT) {
+        HIPCHK(launch_fill_i32(ctx->k_queue.as<int32_t>(), 1, 0, ctx->stream));
+        ka.queue = ctx->k_queue.as<int32_t>();
+        const char* occ = std::getenv("MAG_PERSIST_PER_CU");
+        const int per_cu = occ ? std::max(1, std::atoi(occ)) : 2;
+        grid = (int)std::min<int64_t>(cnt, (int64_t)ncu * per_cu);
+      }
+      HIPCHK(launch_krylov(ka, cap, cls, grid, ctx->stream));
+      HIPCHK(launch_eig(ea, ctx->stream));
+    }
+
+    if (job.consumer == 2) {
+      HIPCHK(launch_cluster_rho(Pbuf, pat_stride, ka.cols, cnt, ka.npat, job.out_off + i0,
+                                job.eps + i0 * job.nu, job.nu_eff + i0, job.nu,
+                                ctx->state.as<MuState>(), job.out, ctx->stream));
+    } else if (job.consumer == 3) {
+      HIPCHK(launch_green(Pbuf, pat_stride, ka.cols, cnt, ka.npat, job.out_off + i0,
+                          job.eps + i0 * job.nu, job.nu_eff + i0, job.nu, job.z, job.nz, job.out,
+                          ctx->stream));
+    }
+    if (job.consumer == 1) {
+      DensityArgs da{};
+      da.P = Pbuf;
+      da.pmode = job.P_store ? 1 : 0;
+      da.pat_stride = pat_stride;
+      da.cols = ka.cols;
+      da.rowptr = ctx->rowptr.as<int64_t>();
+      da.eps = ctx->eps.as<double>();
+      da.nu_eff = ctx->nu_eff.as<int32_t>();
+      da.ncols = cnt;
+      da.nu = job.nu;
+      da.st = ctx->state.as<MuState>();
+      da.rho = job.rho;
+      da.pi = job.pi;
+      HIPCHK(launch_density(da, ctx->stream));
+    }
+    i0 = i1;
+    if (i0 < n) TRY(sync(ctx));  // the next chunk reuses the scratch
+  }
+  return MAG_OK;
+}
+
+int check_opts(mag_ctx* ctx, const mag_opts* o) {
+  if (!o) return fail(ctx, MAG_EINVAL, "opts is NULL");
+  if (o->nu < 1 || o->nu > NU_MAX)
+    return fail(ctx, MAG_EINVAL, "nu must be in 1.." + std::to_string(NU_MAX));
+  if (!(o->kT > 0.0) || !std::isfinite(o->kT)) return fail(ctx, MAG_EINVAL, "kT must be > 0");
+  if (o->workflow != MAG_WORKFLOW_RECOMPUTE && o->workflow != MAG_WORKFLOW_STORE)
+    return fail(ctx, MAG_EINVAL, "unknown workflow");
+  if (o->schedule < MAG_SCHED_AUTO || o->schedule > MAG_SCHED_PLAIN)
+    return fail(ctx, MAG_EINVAL, "unknown schedule");
+  if (!std::isnan(o->mu_fixed) && !std::isfinite(o->mu_fixed))
+    return fail(ctx, MAG_EINVAL, "mu_fixed must be finite or NaN");
+  return MAG_OK;
+}
+
+int ensure_system(mag_ctx* ctx) {
+  if (!ctx) return MAG_EINVAL;
+  if (!ctx->has_system) return fail(ctx, MAG_ESTATE, "no system: call mag_set_system first");
+  HIPCHK(hipSetDevice(ctx->device));
+  return MAG_OK;
+}
+
+// pass 2: rho and pi on the pattern
+int ensure_density(mag_ctx* ctx) {
+  if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve: call mag_solve_columns first");
+  if (ctx->density_ready) return MAG_OK;
+  ALLOC(ctx->rho, sizeof(double) * ctx->nnz);
+  ALLOC(ctx->pi, sizeof(double) * ctx->nnz);
+  Timer tm(ctx->stream);
+  if (ctx->opts.workflow == MAG_WORKFLOW_STORE) {
+    DensityArgs da{};
+    da.P = ctx->P.as<double>();
+    da.pmode = 1;
+    da.pat_stride = PAT_MAX;
+    da.cols = ctx->k_cols.as<int32_t>();
+    da.rowptr = ctx->rowptr.as<int64_t>();
+    da.eps = ctx->eps.as<double>();
+    da.nu_eff = ctx->nu_eff.as<int32_t>();
+    da.ncols = ctx->M;
+    da.nu = ctx->nu;
+    da.st = ctx->state.as<MuState>();
+    da.rho = ctx->rho.as<double>();
+    da.pi = ctx->pi.as<double>();
+    HIPCHK(launch_density(da, ctx->stream));
+  } else {
+    ColumnJob job;
+    job.cols_dev = ctx->k_cols.as<int32_t>();
+    job.cols_host = ctx->h_order;
+    job.nu = ctx->nu;
+    job.breakdown = ctx->opts.breakdown > 0 ? ctx->opts.breakdown : 1e-12;
+    job.schedule = ctx->opts.schedule;
+    // recomputed spectra go to scratch rows so the pass-1 data stay as they are
+    ALLOC(ctx->tmp_cols, sizeof(double) * 2 * ctx->M * ctx->nu + sizeof(int32_t) * ctx->M);
+    job.eps = ctx->tmp_cols.as<double>();
+    job.w = job.eps + ctx->M * ctx->nu;
+    job.nu_eff = reinterpret_cast<int32_t*>(job.w + ctx->M * ctx->nu);
+    job.want_P = 1;
+    job.consumer = 1;
+    job.rho = ctx->rho.as<double>();
+    job.pi = ctx->pi.as<double>();
+    TRY(run_columns(ctx, job));
+  }
+  ctx->stats.t_pass2_ms = tm.stop_ms();
+  TRY(take_errors(ctx, "pass 2"));
+  ctx->density_ready = true;
+  return MAG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int mag_version(void) { return 100; }
+
+const char* mag_last_error(const mag_ctx* ctx) {
+  if (!ctx) return "context is NULL";
+  return ctx->err.c_str();
+}
+
+int mag_create(mag_ctx** out, int device, void* hip_stream) {
+  if (!out) return MAG_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MAG_EHIP;
+  if (device < 0 || device >= ndev) return MAG_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return MAG_EHIP;
+  mag_ctx* ctx = new mag_ctx();
+  ctx->device = device;
+  if (hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return MAG_EHIP;
+    }
+    ctx->own_stream = true;
+  }
+  if (ctx->errflag.reserve(256) != hipSuccess || ctx->state.reserve(sizeof(MuState)) != hipSuccess ||
+      hipMemset(ctx->errflag.p, 0, 256) != hipSuccess ||
+      hipMemset(ctx->state.p, 0, sizeof(MuState)) != hipSuccess) {
+    mag_destroy(ctx);
+    return MAG_ENOMEM;
+  }
+  *out = ctx;
+  return MAG_OK;
+}
+
+void mag_destroy(mag_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  const bool own = ctx->own_stream;
+  hipStream_t s = ctx->stream;
+  delete ctx;  // DevBuf destructors free device memory
+  if (own && s) (void)hipStreamDestroy(s);
+}
+
+void mag_opts_default(mag_opts* o) {
+  if (!o) return;
+  o->nu = 30;
+  o->kT = 0.1;
+  o->n_electrons = 0.0;
+  o->mu_tol = 1e-12;
+  o->mu_fixed = std::nan("");
+  o->breakdown = 1e-12;
+  o->workflow = MAG_WORKFLOW_RECOMPUTE;
+  o->schedule = MAG_SCHED_AUTO;
+}
+
+// ---------------------------------------------------------------------------
+// Slater-Koster
+// ---------------------------------------------------------------------------
+int mag_sk_build(mag_ctx* ctx, const mag_sk_model* model, int64_t n_atoms, const double* pos,
+                 const double cell[3], int mem_kind, int64_t* nnz_out) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!model_ok(model)) return fail(ctx, MAG_EINVAL, "invalid Slater-Koster model");
+  if (n_atoms < 1 || !pos || !cell) return fail(ctx, MAG_EINVAL, "need n_atoms >= 1, pos, cell");
+  if ((int64_t)NORB * n_atoms > (int64_t)INT32_MAX / 2)
+    return fail(ctx, MAG_EUNSUPPORTED, "too many atoms for 32-bit column indices");
+  for (int d = 0; d < 3; ++d)
+    if (!(cell[d] > 2.0 * model->r_cut) || !std::isfinite(cell[d]))
+      return fail(ctx, MAG_EINVAL, "every box length must exceed 2 r_cut");
+  ctx->sk_built = false;
+  const int64_t n = n_atoms;
+  TRY(copy_in(ctx, ctx->sk_pos, pos, sizeof(double) * 3 * n, mem_kind));
+  HIPCHK(launch_check_finite(ctx->sk_pos.as<double>(), 3 * n, ctx->errflag.as<int32_t>(),
+                             ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_build"));
+  CellList cl;
+  HIPCHK(build_cell_list(cl, ctx->sk_pos.as<double>(), n, cell, model->r_cut, ctx->stream));
+  DevBuf cnt;
+  ALLOC(cnt, sizeof(int32_t) * n);
+  HIPCHK(launch_sk_count(ctx->sk_pos.as<double>(), n, cell, model->r_cut, cl, cnt.as<int32_t>(),
+                         ctx->errflag.as<int32_t>(), ctx->stream));
+  std::vector<int32_t> hc(n), hb(n + 1);
+  HIPCHK(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_build"));
+  hb[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if ((int64_t)hb[i] + hc[i] > INT32_MAX / 32)
+      return fail(ctx, MAG_EUNSUPPORTED, "too many blocks");
+    hb[i + 1] = hb[i] + hc[i];
+  }
+  const int64_t nblk = hb[n];
+  const int64_t nnz = 16 * nblk;
+  ALLOC(ctx->sk_bptr, sizeof(int32_t) * (n + 1));
+  ALLOC(ctx->sk_bcol, sizeof(int32_t) * nblk);
+  ALLOC(ctx->sk_rowptr, sizeof(int64_t) * (NORB * n + 1));
+  ALLOC(ctx->sk_colind, sizeof(int32_t) * nnz);
+  ALLOC(ctx->sk_H, sizeof(double) * nnz);
+  ALLOC(ctx->sk_S, sizeof(double) * nnz);
+  HIPCHK(hipMemcpyAsync(ctx->sk_bptr.p, hb.data(), sizeof(int32_t) * (n + 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(launch_sk_fill(ctx->sk_pos.as<double>(), n, cell, model->r_cut, cl,
+                        ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), ctx->stream));
+  HIPCHK(launch_sk_csr(ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), n,
+                       ctx->sk_rowptr.as<int64_t>(), ctx->sk_colind.as<int32_t>(), ctx->stream));
+  ctx->sk_model = to_dev(*model);
+  HIPCHK(launch_sk_values(ctx->sk_model, ctx->sk_pos.as<double>(), n, cell,
+                          ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(),
+                          ctx->sk_H.as<double>(), ctx->sk_S.as<double>(), ctx->stream));
+  TRY(sync(ctx));
+  TRY(take_errors(ctx, "mag_sk_build"));
+  ctx->sk_built = true;
+  ctx->sk_n = n;
+  ctx->sk_nnz = nnz;
+  ctx->sk_nblk = nblk;
+  for (int d = 0; d < 3; ++d) ctx->sk_cell[d] = cell[d];
+  if (nnz_out) *nnz_out = nnz;
+  return MAG_OK;
+}
+
+int mag_sk_get_csr(mag_ctx* ctx, int64_t* rowptr, int32_t* colind, double* H, double* S,
+                   int mem_kind) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!ctx->sk_built) return fail(ctx, MAG_ESTATE, "no Slater-Koster build");
+  HIPCHK(hipSetDevice(ctx->device));
+  TRY(copy_out(ctx, rowptr, ctx->sk_rowptr.p, sizeof(int64_t) * (NORB * ctx->sk_n + 1), mem_kind));
+  TRY(copy_out(ctx, colind, ctx->sk_colind.p, sizeof(int32_t) * ctx->sk_nnz, mem_kind));
+  TRY(copy_out(ctx, H, ctx->sk_H.p, sizeof(double) * ctx->sk_nnz, mem_kind));
+  TRY(copy_out(ctx, S, ctx->sk_S.p, sizeof(double) * ctx->sk_nnz, mem_kind));
+  return sync(ctx);
+}
+
+int mag_sk_values(mag_ctx* ctx, const double* pos, double* H, double* S, int mem_kind) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!ctx->sk_built) return fail(ctx, MAG_ESTATE, "no Slater-Koster build");
+  if (!pos) return fail(ctx, MAG_EINVAL, "pos is NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  TRY(copy_in(ctx, ctx->sk_pos, pos, sizeof(double) * 3 * ctx->sk_n, mem_kind));
+  HIPCHK(launch_check_finite(ctx->sk_pos.as<double>(), 3 * ctx->sk_n, ctx->errflag.as<int32_t>(),
+                             ctx->stream));
+  HIPCHK(launch_sk_values(ctx->sk_model, ctx->sk_pos.as<double>(), ctx->sk_n, ctx->sk_cell,
+                          ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(),
+                          ctx->sk_H.as<double>(), ctx->sk_S.as<double>(), ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_values"));
+  TRY(copy_out(ctx, H, ctx->sk_H.p, sizeof(double) * ctx->sk_nnz, mem_kind));
+  TRY(copy_out(ctx, S, ctx->sk_S.p, sizeof(double) * ctx->sk_nnz, mem_kind));
+  return sync(ctx);
+}
+
+int mag_sk_vjp(mag_ctx* ctx, const double* pos, const double* gH, const double* gS, double* grad,
+               int mem_kind) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!ctx->sk_built) return fail(ctx, MAG_ESTATE, "no Slater-Koster build");
+  if (!pos || !gH || !gS || !grad) return fail(ctx, MAG_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t n = ctx->sk_n, nnz = ctx->sk_nnz;
+  TRY(copy_in(ctx, ctx->sk_pos, pos, sizeof(double) * 3 * n, mem_kind));
+  DevBuf bt, dgh, dgs, dgr;
+  ALLOC(bt, sizeof(int32_t) * ctx->sk_nblk);
+  HIPCHK(launch_block_transpose(ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), n,
+                                bt.as<int32_t>(), ctx->errflag.as<int32_t>(), ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_vjp"));  // every block needs its transpose before the contraction
+  const double* pgh = gH;
+  const double* pgs = gS;
+  if (mem_kind == MAG_HOST) {
+    TRY(copy_in(ctx, dgh, gH, sizeof(double) * nnz, MAG_HOST));
+    TRY(copy_in(ctx, dgs, gS, sizeof(double) * nnz, MAG_HOST));
+    pgh = dgh.as<double>();
+    pgs = dgs.as<double>();
+  }
+  ALLOC(dgr, sizeof(double) * 3 * n);
+  HIPCHK(launch_sk_vjp(ctx->sk_model, ctx->sk_pos.as<double>(), n, ctx->sk_cell,
+                       ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), bt.as<int32_t>(),
+                       pgh, pgs, 1.0, dgr.as<double>(), ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_vjp"));
+  TRY(copy_out(ctx, grad, dgr.p, sizeof(double) * 3 * n, mem_kind));
+  return sync(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// system
+// ---------------------------------------------------------------------------
+int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!sys || sys->n_atoms < 1 || sys->nnz < 1 || !sys->rowptr || !sys->colind || !sys->H ||
+      !sys->S)
+    return fail(ctx, MAG_EINVAL, "system needs n_atoms, nnz, rowptr, colind, H and S");
+  Timer tm(ctx->stream);
+  ctx->has_system = false;
+  ctx->solved = false;
+  ctx->density_ready = false;
+  const int64_t N = sys->n_atoms, M = NORB * N, nnz = sys->nnz;
+  if (M > (int64_t)INT32_MAX / 2)
+    return fail(ctx, MAG_EUNSUPPORTED, "too many atoms for 32-bit column indices");
+
+  // row pointers: host copy and block-complete checks
+  ctx->h_rowptr.assign(M + 1, 0);
+  HIPCHK(hipMemcpyAsync(ctx->h_rowptr.data(), sys->rowptr, sizeof(int64_t) * (M + 1),
+                        mem_kind == MAG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
+                        ctx->stream));
+  TRY(sync(ctx));
+  const std::vector<int64_t>& rp = ctx->h_rowptr;
+  if (rp[0] != 0 || rp[M] != nnz) return fail(ctx, MAG_EINVAL, "rowptr[0] != 0 or rowptr[M] != nnz");
+  std::vector<int32_t> hb(N + 1);
+  ctx->h_bcount.assign(N, 0);
+  hb[0] = 0;
+  for (int64_t J = 0; J < N; ++J) {
+    const int64_t len = rp[NORB * J + 1] - rp[NORB * J];
+    if (len <= 0 || len % NORB != 0 || len / NORB > BLOCKS_MAX)
+      return fail(ctx, MAG_EINVAL, "row " + std::to_string(NORB * J) +
+                                       ": length not a positive multiple of 4 within the block limit");
+    for (int a = 1; a < NORB; ++a)
+      if (rp[NORB * J + a + 1] - rp[NORB * J + a] != len)
+        return fail(ctx, MAG_EINVAL, "rows of atom " + std::to_string(J) + " differ in length");
+    if (rp[NORB * J] != 16 * (int64_t)hb[J])
+      return fail(ctx, MAG_EINVAL, "CSR is not block-complete at atom " + std::to_string(J));
+    ctx->h_bcount[J] = (int32_t)(len / NORB);
+    if ((int64_t)hb[J] + len / NORB > INT32_MAX / 32) return fail(ctx, MAG_EUNSUPPORTED, "too many blocks");
+    hb[J + 1] = hb[J] + (int32_t)(len / NORB);
+  }
+  const int64_t nblk = hb[N];
+  TRY(copy_in(ctx, ctx->rowptr, sys->rowptr, sizeof(int64_t) * (M + 1), mem_kind));
+  ALLOC(ctx->bptr, sizeof(int32_t) * (N + 1));
+  HIPCHK(hipMemcpyAsync(ctx->bptr.p, hb.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice,
+                        ctx->stream));
+  ALLOC(ctx->bcol, sizeof(int32_t) * nblk);
+  ALLOC(ctx->btrans, sizeof(int32_t) * nblk);
+  ALLOC(ctx->bval, sizeof(double) * nblk * 32);
+  {
+    DevBuf ci, hv, sv;
+    const int32_t* pci = sys->colind;
+    const double* phv = sys->H;
+    const double* psv = sys->S;
+    if (mem_kind == MAG_HOST) {
+      TRY(copy_in(ctx, ci, sys->colind, sizeof(int32_t) * nnz, MAG_HOST));
+      TRY(copy_in(ctx, hv, sys->H, sizeof(double) * nnz, MAG_HOST));
+      TRY(copy_in(ctx, sv, sys->S, sizeof(double) * nnz, MAG_HOST));
+      pci = ci.as<int32_t>();
+      phv = hv.as<double>();
+      psv = sv.as<double>();
+    }
+    HIPCHK(launch_check_layout(ctx->rowptr.as<int64_t>(), pci, N, ctx->bptr.as<int32_t>(),
+                               ctx->bcol.as<int32_t>(), ctx->errflag.as<int32_t>(), ctx->stream));
+    HIPCHK(launch_check_finite(phv, nnz, ctx->errflag.as<int32_t>(), ctx->stream));
+    HIPCHK(launch_check_finite(psv, nnz, ctx->errflag.as<int32_t>(), ctx->stream));
+    HIPCHK(launch_to_blocks(ctx->rowptr.as<int64_t>(), phv, psv, N, ctx->bptr.as<int32_t>(),
+                            ctx->bval.as<double>(), ctx->stream));
+    TRY(take_errors(ctx, "mag_set_system"));
+  }
+  HIPCHK(launch_block_transpose(ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(), N,
+                                ctx->btrans.as<int32_t>(), ctx->errflag.as<int32_t>(),
+                                ctx->stream));
+  TRY(take_errors(ctx, "mag_set_system"));
+
+  for (int d = 0; d < 3; ++d) ctx->cell[d] = sys->cell[d];
+  ctx->r_cluster = sys->r_cluster;
+  ctx->has_pos = sys->pos != nullptr;
+  if (ctx->has_pos) {
+    TRY(copy_in(ctx, ctx->pos, sys->pos, sizeof(double) * 3 * N, mem_kind));
+    HIPCHK(launch_check_finite(ctx->pos.as<double>(), 3 * N, ctx->errflag.as<int32_t>(),
+                               ctx->stream));
+    TRY(take_errors(ctx, "mag_set_system"));
+  }
+
+  // clusters
+  std::vector<int64_t> cptr(N + 1);
+  if (sys->clus_ptr && sys->clus_atoms) {
+    HIPCHK(hipMemcpyAsync(cptr.data(), sys->clus_ptr, sizeof(int64_t) * (N + 1),
+                          mem_kind == MAG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
+                          ctx->stream));
+    TRY(sync(ctx));
+    if (cptr[0] != 0) return fail(ctx, MAG_EINVAL, "clus_ptr[0] != 0");
+    for (int64_t J = 0; J < N; ++J) {
+      const int64_t c = cptr[J + 1] - cptr[J];
+      if (c < 1) return fail(ctx, MAG_EINVAL, "empty cluster");
+      if (c > CLUSTER_MAX) return fail(ctx, MAG_EUNSUPPORTED, "cluster above MAG_CLUSTER_MAX atoms");
+    }
+    std::vector<int32_t> hat(cptr[N]);
+    HIPCHK(hipMemcpyAsync(hat.data(), sys->clus_atoms, sizeof(int32_t) * cptr[N],
+                          mem_kind == MAG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
+                          ctx->stream));
+    TRY(sync(ctx));
+    for (int64_t J = 0; J < N; ++J) {
+      bool self = false;
+      for (int64_t a = cptr[J]; a < cptr[J + 1]; ++a) {
+        if (hat[a] < 0 || hat[a] >= N || (a > cptr[J] && hat[a] <= hat[a - 1]))
+          return fail(ctx, MAG_EINVAL, "cluster lists must be ascending atom ids < N");
+        self |= hat[a] == J;
+      }
+      if (!self) return fail(ctx, MAG_EINVAL, "every cluster must contain its own atom");
+    }
+    TRY(copy_in(ctx, ctx->clus_ptr, cptr.data(), sizeof(int64_t) * (N + 1), MAG_HOST));
+    TRY(copy_in(ctx, ctx->clus_atoms, hat.data(), sizeof(int32_t) * cptr[N], MAG_HOST));
+    TRY(sync(ctx));
+  } else if (whole_cell(sys->cell, sys->r_cluster)) {
+    if (N > CLUSTER_MAX)
+      return fail(ctx, MAG_EUNSUPPORTED, "whole-cell cluster above MAG_CLUSTER_MAX atoms");
+    std::vector<int32_t> at(N * N);
+    for (int64_t J = 0; J <= N; ++J) cptr[J] = J * N;
+    for (int64_t J = 0; J < N; ++J)
+      for (int64_t I = 0; I < N; ++I) at[J * N + I] = (int32_t)I;
+    TRY(copy_in(ctx, ctx->clus_ptr, cptr.data(), sizeof(int64_t) * (N + 1), MAG_HOST));
+    TRY(copy_in(ctx, ctx->clus_atoms, at.data(), sizeof(int32_t) * N * N, MAG_HOST));
+    TRY(sync(ctx));
+  } else {
+    if (!ctx->has_pos) return fail(ctx, MAG_EINVAL, "clusters need pos (or clus_ptr/clus_atoms)");
+    CellList cl;
+    HIPCHK(build_cell_list(cl, ctx->pos.as<double>(), N, sys->cell, sys->r_cluster, ctx->stream));
+    DevBuf tmp, cnt;
+    ALLOC(tmp, sizeof(int32_t) * N * (size_t)CLUSTER_MAX);
+    ALLOC(cnt, sizeof(int32_t) * N);
+    HIPCHK(launch_cluster_scan_cv(ctx->pos.as<double>(), N, sys->cell, sys->r_cluster, cl,
+                                  tmp.as<int32_t>(), cnt.as<int32_t>(), ctx->errflag.as<int32_t>(),
+                                  ctx->stream));
+    std::vector<int32_t> hc(N);
+    HIPCHK(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    TRY(take_errors(ctx, "cluster build"));
+    cptr[0] = 0;
+    for (int64_t J = 0; J < N; ++J) cptr[J + 1] = cptr[J] + hc[J];
+    TRY(copy_in(ctx, ctx->clus_ptr, cptr.data(), sizeof(int64_t) * (N + 1), MAG_HOST));
+    ALLOC(ctx->clus_atoms, sizeof(int32_t) * std::max<int64_t>(cptr[N], 1));
+    HIPCHK(launch_cluster_compact(tmp.as<int32_t>(), cnt.as<int32_t>(), ctx->clus_ptr.as<int64_t>(),
+                                  N, ctx->clus_atoms.as<int32_t>(), ctx->stream));
+    TRY(sync(ctx));
+  }
+  ctx->clus_total = cptr[N];
+  ctx->h_clus_size.assign(N, 0);
+  int64_t maxc = 0;
+  for (int64_t J = 0; J < N; ++J) {
+    ctx->h_clus_size[J] = (int32_t)(cptr[J + 1] - cptr[J]);
+    maxc = std::max<int64_t>(maxc, ctx->h_clus_size[J]);
+  }
+  {
+    DevBuf nz;
+    ALLOC(nz, sizeof(int64_t) * N);
+    HIPCHK(launch_cluster_nnz(ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(),
+                              ctx->clus_ptr.as<int64_t>(), ctx->clus_atoms.as<int32_t>(), N,
+                              nz.as<int64_t>(), ctx->stream));
+    std::vector<int64_t> hn(N);
+    HIPCHK(hipMemcpyAsync(hn.data(), nz.p, sizeof(int64_t) * N, hipMemcpyDeviceToHost, ctx->stream));
+    TRY(sync(ctx));
+    ctx->sum_cluster_nnz = std::accumulate(hn.begin(), hn.end(), (int64_t)0);
+  }
+
+  // column order: largest clusters first (ties by column id)
+  std::vector<int32_t> atoms(N);
+  std::iota(atoms.begin(), atoms.end(), 0);
+  std::stable_sort(atoms.begin(), atoms.end(), [&](int32_t a, int32_t b) {
+    return ctx->h_clus_size[a] > ctx->h_clus_size[b];
+  });
+  ctx->h_order.resize(M);
+  for (int64_t i = 0; i < N; ++i)
+    for (int a = 0; a < NORB; ++a) ctx->h_order[NORB * i + a] = NORB * atoms[i] + a;
+  TRY(copy_in(ctx, ctx->k_cols, ctx->h_order.data(), sizeof(int32_t) * M, MAG_HOST));
+  TRY(sync(ctx));
+
+  ctx->N = N;
+  ctx->M = M;
+  ctx->nnz = nnz;
+  ctx->nblk = nblk;
+  ctx->has_system = true;
+  ctx->stats.n_columns = M;
+  ctx->stats.max_cluster = NORB * maxc;
+  ctx->stats.sum_cluster_nnz = ctx->sum_cluster_nnz;
+  ctx->stats.t_set_system_ms = tm.stop_ms();
+  return MAG_OK;
+}
+
+int mag_update_values(mag_ctx* ctx, const double* H, const double* S, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!H || !S) return fail(ctx, MAG_EINVAL, "H and S are required");
+  DevBuf hv, sv;
+  const double* phv = H;
+  const double* psv = S;
+  if (mem_kind == MAG_HOST) {
+    TRY(copy_in(ctx, hv, H, sizeof(double) * ctx->nnz, MAG_HOST));
+    TRY(copy_in(ctx, sv, S, sizeof(double) * ctx->nnz, MAG_HOST));
+    phv = hv.as<double>();
+    psv = sv.as<double>();
+  }
+  HIPCHK(launch_check_finite(phv, ctx->nnz, ctx->errflag.as<int32_t>(), ctx->stream));
+  HIPCHK(launch_check_finite(psv, ctx->nnz, ctx->errflag.as<int32_t>(), ctx->stream));
+  HIPCHK(launch_to_blocks(ctx->rowptr.as<int64_t>(), phv, psv, ctx->N, ctx->bptr.as<int32_t>(),
+                          ctx->bval.as<double>(), ctx->stream));
+  TRY(take_errors(ctx, "mag_update_values"));
+  ctx->solved = false;
+  ctx->density_ready = false;
+  return MAG_OK;
+}
+
+int mag_get_clusters(mag_ctx* ctx, int64_t* clus_ptr, int32_t* clus_atoms, int64_t* total_out,
+                     int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (total_out) *total_out = ctx->clus_total;
+  TRY(copy_out(ctx, clus_ptr, ctx->clus_ptr.p, sizeof(int64_t) * (ctx->N + 1), mem_kind));
+  TRY(copy_out(ctx, clus_atoms, ctx->clus_atoms.p, sizeof(int32_t) * ctx->clus_total, mem_kind));
+  return sync(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_band,
+                      double* A_free) {
+  TRY(ensure_system(ctx));
+  TRY(check_opts(ctx, opts));
+  const bool fixed = !std::isnan(opts->mu_fixed);
+  if (!fixed && !(opts->n_electrons > 0.0 && opts->n_electrons < 2.0 * (double)ctx->M))
+    return fail(ctx, MAG_EBRACKET, "n_electrons must lie in (0, 2M)");
+  ctx->solved = false;
+  ctx->density_ready = false;
+  ctx->opts = *opts;
+  const int nu = opts->nu;
+  ctx->nu = nu;
+  const int64_t M = ctx->M;
+  ALLOC(ctx->eps, sizeof(double) * M * nu);
+  ALLOC(ctx->w, sizeof(double) * M * nu);
+  ALLOC(ctx->nu_eff, sizeof(int32_t) * M);
+  const bool store = opts->workflow == MAG_WORKFLOW_STORE;
+  if (store) ALLOC(ctx->P, sizeof(double) * ctx->nnz * nu);
+
+  // ---- pass 1
+  Timer t1(ctx->stream);
+  ColumnJob job;
+  job.cols_dev = ctx->k_cols.as<int32_t>();
+  job.cols_host = ctx->h_order;
+  job.nu = nu;
+  job.breakdown = opts->breakdown > 0 ? opts->breakdown : 1e-12;
+  job.schedule = opts->schedule;
+  job.eps = ctx->eps.as<double>();
+  job.w = ctx->w.as<double>();
+  job.nu_eff = ctx->nu_eff.as<int32_t>();
+  job.want_P = store ? 1 : 0;
+  job.P_store = store ? ctx->P.as<double>() : nullptr;
+  TRY(run_columns(ctx, job));
+  ctx->stats.t_pass1_ms = t1.stop_ms();
+  TRY(take_errors(ctx, "pass 1"));
+
+  // ---- chemical potential and energies
+  Timer t2(ctx->stream);
+  const int grid = std::min<int64_t>(1024, std::max<int64_t>(1, (M * nu + 2047) / 2048));
+  ALLOC(ctx->partials, sizeof(double) * 64 * (size_t)grid);
+  MuState h{};
+  h.ne = opts->n_electrons;
+  h.kT = opts->kT;
+  h.tol = opts->mu_tol > 0 ? opts->mu_tol : 1e-12;
+  h.counter = 0;
+  if (fixed) {
+    h.mu = opts->mu_fixed;
+    h.done = 1;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->state.p, &h, sizeof(MuState), hipMemcpyHostToDevice, ctx->stream));
+  MuState* st = ctx->state.as<MuState>();
+  if (!fixed) {
+    HIPCHK(launch_mu_init(ctx->eps.as<double>(), ctx->w.as<double>(), ctx->nu_eff.as<int32_t>(),
+                          M, nu, st, ctx->partials.as<double>(), grid, ctx->stream));
+    MuState hs{};
+    HIPCHK(hipMemcpyAsync(&hs, st, sizeof(MuState), hipMemcpyDeviceToHost, ctx->stream));
+    TRY(sync(ctx));
+    if (hs.err & KERR_NONFINITE) return fail(ctx, MAG_ENONFINITE, "non-finite Ritz data");
+    const double width = hs.hi - hs.lo;
+    const int levels = width > h.tol ? (int)std::ceil(std::log2(width / h.tol)) + 2 : 1;
+    const int rounds = (levels + mu_levels_per_round() - 1) / mu_levels_per_round();
+    for (int r = 0; r < rounds; ++r)
+      HIPCHK(launch_mu_round(ctx->eps.as<double>(), ctx->w.as<double>(),
+                             ctx->nu_eff.as<int32_t>(), M, nu, st, ctx->partials.as<double>(),
+                             grid, ctx->stream));
+  }
+  HIPCHK(launch_energy(ctx->eps.as<double>(), ctx->w.as<double>(), ctx->nu_eff.as<int32_t>(), M,
+                       nu, st, ctx->partials.as<double>(), grid, ctx->stream));
+  HIPCHK(hipMemcpyAsync(&ctx->h_state, st, sizeof(MuState), hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
+  ctx->stats.t_mu_ms = t2.stop_ms();
+  ctx->stats.bisect_levels = ctx->h_state.levels;
+  if (!fixed && !ctx->h_state.done)
+    return fail(ctx, MAG_EBRACKET, "bisection did not reach the tolerance");
+  if (!std::isfinite(ctx->h_state.E) || !std::isfinite(ctx->h_state.mu))
+    return fail(ctx, MAG_ENONFINITE, "non-finite energy");
+  ctx->solved = true;
+  if (mu) *mu = ctx->h_state.mu;
+  if (E_band) *E_band = ctx->h_state.E;
+  if (A_free) *A_free = ctx->h_state.E - opts->kT * ctx->h_state.S_ent;
+  return MAG_OK;
+}
+
+int mag_spectra(mag_ctx* ctx, double* eps, double* w, int32_t* nu_eff, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve");
+  TRY(copy_out(ctx, eps, ctx->eps.p, sizeof(double) * ctx->M * ctx->nu, mem_kind));
+  TRY(copy_out(ctx, w, ctx->w.p, sizeof(double) * ctx->M * ctx->nu, mem_kind));
+  TRY(copy_out(ctx, nu_eff, ctx->nu_eff.p, sizeof(int32_t) * ctx->M, mem_kind));
+  return sync(ctx);
+}
+
+int mag_energy(mag_ctx* ctx, double* E_band, double* A_free, double* N_check, double* S_ent) {
+  TRY(ensure_system(ctx));
+  if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve");
+  if (E_band) *E_band = ctx->h_state.E;
+  if (A_free) *A_free = ctx->h_state.E - ctx->opts.kT * ctx->h_state.S_ent;
+  if (N_check) *N_check = ctx->h_state.N;
+  if (S_ent) *S_ent = ctx->h_state.S_ent;
+  return MAG_OK;
+}
+
+static int upload_cols(mag_ctx* ctx, const int32_t* cols, int64_t n, int mem_kind,
+                       std::vector<int32_t>& host) {
+  host.resize(n);
+  if (n == 0) return MAG_OK;
+  HIPCHK(hipMemcpyAsync(host.data(), cols, sizeof(int32_t) * n,
+                        mem_kind == MAG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
+                        ctx->stream));
+  TRY(sync(ctx));
+  for (int32_t c : host)
+    if (c < 0 || c >= ctx->M) return fail(ctx, MAG_EINVAL, "column id out of range");
+  return MAG_OK;
+}
+
+int mag_column_spectra(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols, int64_t n,
+                       double* eps, double* w, int32_t* nu_eff, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  TRY(check_opts(ctx, opts));
+  if (n < 0 || (n > 0 && !cols)) return fail(ctx, MAG_EINVAL, "bad column list");
+  if (n == 0) return MAG_OK;
+  ColumnJob job;
+  TRY(upload_cols(ctx, cols, n, mem_kind, job.cols_host));
+  DevBuf dcols, out;
+  TRY(copy_in(ctx, dcols, job.cols_host.data(), sizeof(int32_t) * n, MAG_HOST));
+  ALLOC(out, sizeof(double) * 2 * n * opts->nu + sizeof(int32_t) * n);
+  job.cols_dev = dcols.as<int32_t>();
+  job.nu = opts->nu;
+  job.breakdown = opts->breakdown > 0 ? opts->breakdown : 1e-12;
+  job.schedule = opts->schedule;
+  job.eps = out.as<double>();
+  job.w = job.eps + n * opts->nu;
+  job.nu_eff = reinterpret_cast<int32_t*>(job.w + n * opts->nu);
+  job.out_by_slot = 1;
+  TRY(run_columns(ctx, job));
+  TRY(take_errors(ctx, "mag_column_spectra"));
+  TRY(copy_out(ctx, eps, job.eps, sizeof(double) * n * opts->nu, mem_kind));
+  TRY(copy_out(ctx, w, job.w, sizeof(double) * n * opts->nu, mem_kind));
+  TRY(copy_out(ctx, nu_eff, job.nu_eff, sizeof(int32_t) * n, mem_kind));
+  return sync(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// pass 2
+// ---------------------------------------------------------------------------
+int mag_density_matrix(mag_ctx* ctx, double* rho_csr, double* pi_csr, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  TRY(ensure_density(ctx));
+  TRY(copy_out(ctx, rho_csr, ctx->rho.p, sizeof(double) * ctx->nnz, mem_kind));
+  TRY(copy_out(ctx, pi_csr, ctx->pi.p, sizeof(double) * ctx->nnz, mem_kind));
+  return sync(ctx);
+}
+
+// Krylov pass over selected columns writing every cluster row, then a
+// per-chunk consumer (2: rho on the whole cluster column, 3: G(z) columns)
+static int full_columns(mag_ctx* ctx, const mag_opts* o, const std::vector<int32_t>& hcols,
+                        int consumer, const double* zdev, int nz, double* out_dev,
+                        std::vector<int64_t>& off) {
+  const int64_t n = (int64_t)hcols.size();
+  const int64_t per = consumer == 3 ? 2 * (int64_t)nz : 1;
+  std::vector<int64_t> soff(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) soff[i + 1] = soff[i] + NORB * ctx->h_clus_size[hcols[i] >> 2];
+  off = soff;
+  for (auto& x : soff) x *= (consumer == 3 ? (int64_t)nz : 1);  // complex-pair index base
+  DevBuf dcols, spec, doff;
+  TRY(copy_in(ctx, dcols, hcols.data(), sizeof(int32_t) * n, MAG_HOST));
+  TRY(copy_in(ctx, doff, soff.data(), sizeof(int64_t) * (n + 1), MAG_HOST));
+  ALLOC(spec, sizeof(double) * 2 * n * o->nu + sizeof(int32_t) * n);
+  (void)per;
+  ColumnJob job;
+  job.cols_dev = dcols.as<int32_t>();
+  job.cols_host = hcols;
+  job.nu = o->nu;
+  job.breakdown = o->breakdown > 0 ? o->breakdown : 1e-12;
+  job.schedule = MAG_SCHED_GRID;
+  job.full = 1;
+  job.eps = spec.as<double>();
+  job.w = job.eps + n * o->nu;
+  job.nu_eff = reinterpret_cast<int32_t*>(job.w + n * o->nu);
+  job.out_by_slot = 1;
+  job.want_P = 1;
+  job.consumer = consumer;
+  job.out_off = doff.as<int64_t>();
+  job.out = out_dev;
+  job.z = zdev;
+  job.nz = nz;
+  TRY(run_columns(ctx, job));
+  TRY(sync(ctx));
+  return take_errors(ctx, "cluster columns");
+}
+
+int mag_cluster_columns(mag_ctx* ctx, const int32_t* cols, int64_t n, double* rho_out,
+                        int64_t* offsets, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve");
+  if (n < 0 || (n > 0 && !cols)) return fail(ctx, MAG_EINVAL, "bad column list");
+  std::vector<int32_t> hcols;
+  TRY(upload_cols(ctx, cols, n, mem_kind, hcols));
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + NORB * ctx->h_clus_size[hcols[i] >> 2];
+  if (offsets) std::copy(off.begin(), off.end(), offsets);
+  if (!rho_out || n == 0) return MAG_OK;
+  DevBuf out;
+  double* dst = rho_out;
+  if (mem_kind == MAG_HOST) {
+    ALLOC(out, sizeof(double) * std::max<int64_t>(off[n], 1));
+    dst = out.as<double>();
+  }
+  std::vector<int64_t> o2;
+  TRY(full_columns(ctx, &ctx->opts, hcols, 2, nullptr, 0, dst, o2));
+  if (mem_kind == MAG_HOST) TRY(copy_out(ctx, rho_out, dst, sizeof(double) * off[n], MAG_HOST));
+  return sync(ctx);
+}
+
+int mag_green_columns(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols, int64_t n,
+                      const double* z, int nz, double* G_out, int64_t* offsets, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  TRY(check_opts(ctx, opts));
+  if (n < 0 || (n > 0 && !cols) || nz < 0 || (nz > 0 && !z))
+    return fail(ctx, MAG_EINVAL, "bad column or energy list");
+  std::vector<int32_t> hcols;
+  TRY(upload_cols(ctx, cols, n, mem_kind, hcols));
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + NORB * ctx->h_clus_size[hcols[i] >> 2];
+  if (offsets) std::copy(off.begin(), off.end(), offsets);
+  if (!G_out || n == 0 || nz == 0) return MAG_OK;
+  DevBuf dz, out;
+  TRY(copy_in(ctx, dz, z, sizeof(double) * 2 * nz, MAG_HOST));
+  double* dst = G_out;
+  if (mem_kind == MAG_HOST) {
+    ALLOC(out, sizeof(double) * 2 * std::max<int64_t>(off[n] * nz, 1));
+    dst = out.as<double>();
+  }
+  std::vector<int64_t> o2;
+  TRY(full_columns(ctx, opts, hcols, 3, dz.as<double>(), nz, dst, o2));
+  if (mem_kind == MAG_HOST)
+    TRY(copy_out(ctx, G_out, dst, sizeof(double) * 2 * off[n] * nz, MAG_HOST));
+  return sync(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// derivatives
+// ---------------------------------------------------------------------------
+int mag_backward(mag_ctx* ctx, double gA, double* dAdH_csr, double* dAdS_csr, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  TRY(ensure_density(ctx));
+  if (!std::isfinite(gA)) return fail(ctx, MAG_EINVAL, "gA must be finite");
+  DevBuf tmp;
+  if (dAdH_csr) {
+    double* dst = dAdH_csr;
+    if (mem_kind == MAG_HOST) {
+      ALLOC(tmp, sizeof(double) * ctx->nnz);
+      dst = tmp.as<double>();
+    }
+    HIPCHK(launch_scale_copy(ctx->rho.as<double>(), ctx->nnz, gA, dst, ctx->stream));
+    if (mem_kind == MAG_HOST) TRY(copy_out(ctx, dAdH_csr, dst, sizeof(double) * ctx->nnz, MAG_HOST));
+    TRY(sync(ctx));
+  }
+  if (dAdS_csr) {
+    double* dst = dAdS_csr;
+    if (mem_kind == MAG_HOST) {
+      ALLOC(tmp, sizeof(double) * ctx->nnz);
+      dst = tmp.as<double>();
+    }
+    HIPCHK(launch_scale_copy(ctx->pi.as<double>(), ctx->nnz, -gA, dst, ctx->stream));
+    if (mem_kind == MAG_HOST) TRY(copy_out(ctx, dAdS_csr, dst, sizeof(double) * ctx->nnz, MAG_HOST));
+    TRY(sync(ctx));
+  }
+  return MAG_OK;
+}
+
+int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!model_ok(model)) return fail(ctx, MAG_EINVAL, "invalid Slater-Koster model");
+  if (!F) return fail(ctx, MAG_EINVAL, "F is NULL");
+  if (!ctx->has_pos) return fail(ctx, MAG_EINVAL, "forces need mag_system.pos");
+  TRY(ensure_density(ctx));
+  Timer tm(ctx->stream);
+  DevBuf grad, out;
+  ALLOC(grad, sizeof(double) * 3 * ctx->N);
+  HIPCHK(launch_sk_vjp(to_dev(*model), ctx->pos.as<double>(), ctx->N, ctx->cell,
+                       ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(),
+                       ctx->btrans.as<int32_t>(), ctx->rho.as<double>(), ctx->pi.as<double>(),
+                       -1.0, grad.as<double>(), ctx->stream));
+  double* dst = F;
+  if (mem_kind == MAG_HOST) {
+    ALLOC(out, sizeof(double) * 3 * ctx->N);
+    dst = out.as<double>();
+  }
+  HIPCHK(launch_scale_copy(grad.as<double>(), 3 * ctx->N, -1.0, dst, ctx->stream));
+  if (mem_kind == MAG_HOST) TRY(copy_out(ctx, F, dst, sizeof(double) * 3 * ctx->N, MAG_HOST));
+  TRY(sync(ctx));
+  ctx->stats.t_forces_ms = tm.stop_ms();
+  return take_errors(ctx, "mag_forces");
+}
+
+int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
+  if (!ctx || !out) return MAG_EINVAL;
+  int64_t bytes = 0;
+  const DevBuf* bufs[] = {&ctx->sk_pos, &ctx->sk_bptr, &ctx->sk_bcol, &ctx->sk_rowptr,
+                          &ctx->sk_colind, &ctx->sk_H, &ctx->sk_S, &ctx->rowptr, &ctx->bptr,
+                          &ctx->bcol, &ctx->btrans, &ctx->bval, &ctx->pos, &ctx->clus_ptr,
+                          &ctx->clus_atoms, &ctx->eps, &ctx->w, &ctx->nu_eff, &ctx->state,
+                          &ctx->partials, &ctx->P, &ctx->rho, &ctx->pi, &ctx->k_hs,
+                          &ctx->k_urow, &ctx->k_qpat, &ctx->k_nu, &ctx->k_npat, &ctx->k_cols,
+                          &ctx->k_queue, &ctx->errflag, &ctx->tmp_cols, &ctx->tmp_off,
+                          &ctx->tmp_out};
+  for (const DevBuf* b : bufs) bytes += (int64_t)b->bytes;
+  ctx->stats.device_bytes = bytes;
+  *out = ctx->stats;
+  return MAG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+// Internal declarations of libmag: context, device buffers, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mag.h"
+
+namespace mag {
+
+constexpr int NORB = MAG_NORB;
+constexpr int NU_MAX = MAG_NU_MAX;
+constexpr int CLUSTER_MAX = MAG_CLUSTER_MAX;
+constexpr int BLOCKS_MAX = MAG_BLOCKS_MAX;
+constexpr int PAT_MAX = NORB * BLOCKS_MAX;      // pattern entries of one CSR row
+constexpr int NC_MAX = NORB * CLUSTER_MAX;      // cluster orbitals
+constexpr double G_SPIN = 2.0;
+
+// error flags raised by kernels (bit mask in a device int)
+enum KernelError : int {
+  KERR_NONE = 0,
+  KERR_NOTPD = 1,       // projected overlap not positive definite
+  KERR_NONFINITE = 2,   // NaN / Inf met
+  KERR_PATTERN = 4,     // a pattern atom outside the cluster
+  KERR_CAPACITY = 8,    // a fixed-size buffer would overflow
+  KERR_LAYOUT = 16,     // CSR not block-complete
+  KERR_BRACKET = 32,    // no sign change of N(mu) - N_e in the bracket
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // grow-only allocation; contents are not preserved
+  hipError_t reserve(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = n;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// state of the chemical-potential search and of the energy sums (device)
+struct MuState {
+  double lo, hi, mu;
+  double E, S_ent, N;
+  double ne, kT, tol;
+  int done;
+  int levels;
+  int err;
+  unsigned counter;
+  double emin, emax;
+  double pad[4];
+};
+
+struct KrylovArgs {
+  const int32_t* bptr;     // N + 1 block-row pointers
+  const int32_t* bcol;     // block column atom ids
+  const double* bval;      // nblk x 32: H block (row major) then S block
+  const int64_t* clus_ptr; // N + 1
+  const int32_t* clus_atoms;
+  const int32_t* cols;     // columns of this launch, in slot order
+  int64_t ncols;
+  int32_t* queue;          // persistent queue counter, or nullptr
+  int nu;                  // requested Krylov dimension (<= template capacity)
+  double breakdown;
+  double* hs;              // per slot: h (NU x NU, column k rows i<=k) then s
+  double* urow;            // per slot: row l of Q (NU)
+  double* qpat;            // per slot: pat_stride x cap rows of Q on the pattern
+  int32_t* nu_eff;         // per slot
+  int32_t* npat;           // per slot: rows written to qpat
+  int32_t* err;            // error flag bits
+  int cap;                 // NU capacity used for strides
+  int pat_stride;          // rows per slot in qpat (PAT_MAX, or NC_MAX when full)
+  int full;                // 1: write every cluster row of Q, not only the pattern
+};
+
+struct EigArgs {
+  const double* hs;
+  const double* urow;
+  const double* qpat;
+  const int32_t* nu_eff_in;   // per slot
+  const int32_t* cols;        // per slot global column
+  const int64_t* rowptr;      // CSR row pointers (M + 1)
+  int64_t ncols;
+  int cap;                    // stride capacity of hs/urow/qpat
+  int nu;                     // stride of eps/w outputs
+  double* eps;                // M x nu (indexed by global column)
+  double* w;                  // M x nu
+  int32_t* nu_eff_out;        // M
+  const int32_t* npat;        // per slot pattern rows
+  double* P;                  // Y d on the pattern, or nullptr
+  int pmode;                  // 1: P row base = rowptr[j]; 0: slot * pat_stride
+  int pat_stride;
+  int out_by_slot;            // 1: eps/w/nu_eff rows indexed by slot instead of column
+  int32_t* err;
+};
+
+struct DensityArgs {
+  const double* P;
+  int pmode;              // as in EigArgs
+  int pat_stride;
+  const int32_t* cols;    // per slot
+  const int64_t* rowptr;
+  const double* eps;
+  const int32_t* nu_eff;
+  int64_t ncols;
+  int nu;
+  const MuState* st;
+  double* rho;
+  double* pi;
+};
+
+// --------------------------------------------------------------------------
+// launchers (implemented in the .hip files)
+// --------------------------------------------------------------------------
+hipError_t launch_krylov(const KrylovArgs& a, int cap, int rows_per_thread, int grid,
+                         hipStream_t s);
+int krylov_capacity(int nu);  // template capacity used for nu (0 if unsupported)
+int krylov_threads();
+hipError_t launch_eig(const EigArgs& a, hipStream_t s);
+hipError_t launch_density(const DensityArgs& a, hipStream_t s);
+
+hipError_t launch_mu_init(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
+                          int nu, MuState* st, double* partials, int grid, hipStream_t s);
+hipError_t launch_mu_round(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
+                           int nu, MuState* st, double* partials, int grid, hipStream_t s);
+hipError_t launch_energy(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
+                         int nu, MuState* st, double* partials, int grid, hipStream_t s);
+int mu_points_per_round();
+int mu_levels_per_round();
+
+// clusters
+hipError_t launch_cluster_scan_cv(const double* pos, int64_t n, const double cell[3], double rc,
+                                  const struct CellList& cl, int32_t* tmp, int32_t* cnt,
+                                  int32_t* err, hipStream_t s);
+hipError_t launch_cluster_nnz(const int32_t* bptr, const int32_t* bcol, const int64_t* clus_ptr,
+                              const int32_t* clus_atoms, int64_t n, int64_t* out, hipStream_t s);
+hipError_t launch_cluster_compact(const int32_t* tmp, const int32_t* cnt, const int64_t* ptr,
+                                  int64_t n, int32_t* atoms, hipStream_t s);
+
+// cell list (shared by the SK pattern and the clusters)
+struct CellList {
+  int ncell[3] = {0, 0, 0};
+  bool brute = true;
+  DevBuf cell_of, cell_count, cell_start, cell_atoms;
+};
+hipError_t build_cell_list(CellList& cl, const double* pos_dev, int64_t n, const double cell[3],
+                           double rmin, hipStream_t s);
+
+// Slater-Koster
+struct SKModelDev {
+  double es, ep;
+  double vh[4];  // ss, sp, pp_sigma, pp_pi for H
+  double vs[4];  // same for S - I
+  double r0, r_on, r_cut;
+};
+hipError_t launch_sk_count(const double* pos, int64_t n, const double cell[3], double rc,
+                           const CellList& cl, int32_t* cnt, int32_t* err, hipStream_t s);
+hipError_t launch_sk_fill(const double* pos, int64_t n, const double cell[3], double rc,
+                          const CellList& cl, const int32_t* bptr, int32_t* bcol, hipStream_t s);
+hipError_t launch_sk_csr(const int32_t* bptr, const int32_t* bcol, int64_t n, int64_t* rowptr,
+                         int32_t* colind, hipStream_t s);
+hipError_t launch_sk_values(const SKModelDev& m, const double* pos, int64_t n,
+                            const double cell[3], const int32_t* bptr, const int32_t* bcol,
+                            double* H, double* S, hipStream_t s);
+hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
+                         const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
+                         const double* gH, const double* gS, double sign_gS, double* grad,
+                         hipStream_t s);
+
+// system conversion
+hipError_t launch_check_layout(const int64_t* rowptr, const int32_t* colind, int64_t n,
+                               const int32_t* bptr, int32_t* bcol, int32_t* err, hipStream_t s);
+hipError_t launch_to_blocks(const int64_t* rowptr, const double* H, const double* S, int64_t n,
+                            const int32_t* bptr, double* bval, hipStream_t s);
+hipError_t launch_block_transpose(const int32_t* bptr, const int32_t* bcol, int64_t n,
+                                  int32_t* btrans, int32_t* err, hipStream_t s);
+hipError_t launch_check_finite(const double* x, int64_t n, int32_t* err, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_scale_copy(const double* x, int64_t n, double a, double* y, hipStream_t s);
+hipError_t launch_cluster_rho(const double* P, int pat_stride, const int32_t* cols, int64_t ncols,
+                              const int32_t* npat, const int64_t* out_off, const double* eps,
+                              const int32_t* nu_eff, int nu, const MuState* st, double* out,
+                              hipStream_t s);
+hipError_t launch_green(const double* P, int pat_stride, const int32_t* cols, int64_t ncols,
+                        const int32_t* npat, const int64_t* out_off, const double* eps,
+                        const int32_t* nu_eff, int nu, const double* z, int nz, double* out,
+                        hipStream_t s);
+
+}  // namespace mag
+
+// the opaque context of the C ABI
+struct mag_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // Slater-Koster build
+  bool sk_built = false;
+  int64_t sk_n = 0, sk_nnz = 0, sk_nblk = 0;
+  double sk_cell[3] = {0, 0, 0};
+  mag::SKModelDev sk_model{};
+  mag::DevBuf sk_pos, sk_bptr, sk_bcol, sk_rowptr, sk_colind, sk_H, sk_S;
+
+  // system
+  bool has_system = false;
+  int64_t N = 0, M = 0, nnz = 0, nblk = 0;
+  double cell[3] = {0, 0, 0};
+  double r_cluster = 0.0;
+  bool has_pos = false;
+  mag::DevBuf rowptr, bptr, bcol, btrans, bval, pos, clus_ptr, clus_atoms;
+  int64_t clus_total = 0;
+  std::vector<int32_t> h_clus_size;   // atoms per cluster
+  std::vector<int32_t> h_bcount;      // blocks per block row
+  std::vector<int64_t> h_rowptr;      // CSR row pointers (host copy)
+  std::vector<int32_t> h_order;       // columns, largest clusters first
+  int64_t sum_cluster_nnz = 0;
+
+  // solve state
+  bool solved = false;
+  bool density_ready = false;
+  mag_opts opts{};
+  int nu = 0;
+  mag::DevBuf eps, w, nu_eff, state, partials, P, rho, pi;
+  mag::DevBuf k_hs, k_urow, k_qpat, k_nu, k_npat, k_cols, k_queue, errflag;
+  mag::DevBuf tmp_cols, tmp_off, tmp_out;
+  int64_t batch_cols = 0;
+  mag::MuState h_state{};
+
+  mag_stats stats{};
+};

@@ -1,0 +1,486 @@
+// Tight-binding matrices from positions (two-center Slater-Koster sp model),
+// their vector-Jacobian product (forces through the density matrix), the cell
+// list shared with the cluster builder, and the cluster lists themselves.
+//
+// The letter builds H and S redundantly on every node instead of exchanging
+// them; here they are built once on the device by one thread per block row.
+#include <algorithm>
+
+#include "mag_internal.h"
+
+namespace mag {
+
+constexpr int STPB = 128;
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+// ---------------------------------------------------------------------------
+struct Box {
+  double L[3];
+};
+
+__device__ __forceinline__ void min_image(const Box& b, double& dx, double& dy, double& dz) {
+  dx -= b.L[0] * rint(dx / b.L[0]);
+  dy -= b.L[1] * rint(dy / b.L[1]);
+  dz -= b.L[2] * rint(dz / b.L[2]);
+}
+
+struct CellView {
+  int nc[3];
+  int brute;
+  const int32_t* start;
+  const int32_t* atoms;
+};
+
+__device__ __forceinline__ int cell_coord(double x, double L, int nc) {
+  double f = x - L * floor(x / L);
+  int c = (int)(f / L * nc);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+template <typename F>
+__device__ __forceinline__ void for_candidates(const CellView& cv, const double* pos, int64_t n,
+                                               const Box& box, int64_t i, F&& f) {
+  if (cv.brute) {
+    for (int64_t k = 0; k < n; ++k) f((int)k);
+    return;
+  }
+  const int cx = cell_coord(pos[3 * i], box.L[0], cv.nc[0]);
+  const int cy = cell_coord(pos[3 * i + 1], box.L[1], cv.nc[1]);
+  const int cz = cell_coord(pos[3 * i + 2], box.L[2], cv.nc[2]);
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = (cx + dx + cv.nc[0]) % cv.nc[0];
+        const int y = (cy + dy + cv.nc[1]) % cv.nc[1];
+        const int z = (cz + dz + cv.nc[2]) % cv.nc[2];
+        const int c = (z * cv.nc[1] + y) * cv.nc[0] + x;
+        for (int a = cv.start[c]; a < cv.start[c + 1]; ++a) f(cv.atoms[a]);
+      }
+}
+
+__global__ void cell_assign_kernel(const double* pos, int64_t n, Box box, int nc0, int nc1,
+                                   int nc2, int32_t* cell_of, int32_t* count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = cell_coord(pos[3 * i], box.L[0], nc0);
+  const int y = cell_coord(pos[3 * i + 1], box.L[1], nc1);
+  const int z = cell_coord(pos[3 * i + 2], box.L[2], nc2);
+  const int c = (z * nc1 + y) * nc0 + x;
+  cell_of[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+__global__ void cell_fill_kernel(const int32_t* cell_of, int64_t n, const int32_t* start,
+                                 int32_t* fillpos, int32_t* atoms) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int slot = atomicAdd(&fillpos[c], 1);
+  atoms[start[c] + slot] = (int)i;
+}
+
+static unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+hipError_t build_cell_list(CellList& cl, const double* pos, int64_t n, const double cell[3],
+                           double rmin, hipStream_t s) {
+  cl.brute = false;
+  for (int d = 0; d < 3; ++d) {
+    cl.ncell[d] = (int)std::floor(cell[d] / rmin);
+    if (cl.ncell[d] < 3) cl.brute = true;
+  }
+  if (cl.brute || n == 0) {
+    cl.brute = true;
+    return hipSuccess;
+  }
+  const int64_t ncells = (int64_t)cl.ncell[0] * cl.ncell[1] * cl.ncell[2];
+  hipError_t e;
+  if ((e = cl.cell_of.reserve(n * 4)) != hipSuccess) return e;
+  if ((e = cl.cell_count.reserve((ncells + 1) * 4)) != hipSuccess) return e;
+  if ((e = cl.cell_start.reserve((ncells + 1) * 4)) != hipSuccess) return e;
+  if ((e = cl.cell_atoms.reserve(n * 4)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(cl.cell_count.p, 0, (ncells + 1) * 4, s)) != hipSuccess) return e;
+  Box box{{cell[0], cell[1], cell[2]}};
+  hipLaunchKernelGGL(cell_assign_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, n, box,
+                     cl.ncell[0], cl.ncell[1], cl.ncell[2], cl.cell_of.as<int32_t>(),
+                     cl.cell_count.as<int32_t>());
+  std::vector<int32_t> cnt(ncells), start(ncells + 1);
+  if ((e = hipMemcpyAsync(cnt.data(), cl.cell_count.p, ncells * 4, hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  start[0] = 0;
+  for (int64_t c = 0; c < ncells; ++c) start[c + 1] = start[c] + cnt[c];
+  if ((e = hipMemcpyAsync(cl.cell_start.p, start.data(), (ncells + 1) * 4, hipMemcpyHostToDevice,
+                          s)) != hipSuccess)
+    return e;
+  if ((e = hipMemsetAsync(cl.cell_count.p, 0, (ncells + 1) * 4, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(cell_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                     cl.cell_of.as<int32_t>(), n, cl.cell_start.as<int32_t>(),
+                     cl.cell_count.as<int32_t>(), cl.cell_atoms.as<int32_t>());
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);  // keep the host vectors alive until the copies are done
+}
+
+static CellView view_of(const CellList& cl) {
+  CellView v;
+  v.nc[0] = cl.ncell[0];
+  v.nc[1] = cl.ncell[1];
+  v.nc[2] = cl.ncell[2];
+  v.brute = cl.brute ? 1 : 0;
+  v.start = cl.cell_start.as<int32_t>();
+  v.atoms = cl.cell_atoms.as<int32_t>();
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// sparsity pattern: atoms closer than r_cut, plus self
+// ---------------------------------------------------------------------------
+__global__ void sk_count_kernel(const double* pos, int64_t n, Box box, double rc2, CellView cv,
+                                int32_t* cnt, int32_t* err) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  int c = 1;
+  for_candidates(cv, pos, n, box, i, [&](int k) {
+    if (k == i) return;
+    double dx = pos[3 * k] - xi, dy = pos[3 * k + 1] - yi, dz = pos[3 * k + 2] - zi;
+    min_image(box, dx, dy, dz);
+    if (dx * dx + dy * dy + dz * dz < rc2) ++c;
+  });
+  cnt[i] = c;
+  if (c > BLOCKS_MAX) atomicOr(err, (int)KERR_CAPACITY);
+}
+
+__global__ void sk_fill_kernel(const double* pos, int64_t n, Box box, double rc2, CellView cv,
+                               const int32_t* bptr, int32_t* bcol) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  int list[BLOCKS_MAX];
+  int c = 0;
+  list[c++] = (int)i;
+  for_candidates(cv, pos, n, box, i, [&](int k) {
+    if (k == i) return;
+    double dx = pos[3 * k] - xi, dy = pos[3 * k + 1] - yi, dz = pos[3 * k + 2] - zi;
+    min_image(box, dx, dy, dz);
+    if (dx * dx + dy * dy + dz * dz < rc2 && c < BLOCKS_MAX) list[c++] = k;
+  });
+  for (int a = 1; a < c; ++a) {  // insertion sort, ascending atom id
+    const int v = list[a];
+    int b = a - 1;
+    while (b >= 0 && list[b] > v) {
+      list[b + 1] = list[b];
+      --b;
+    }
+    list[b + 1] = v;
+  }
+  const int base = bptr[i];
+  for (int a = 0; a < c; ++a) bcol[base + a] = list[a];
+}
+
+__global__ void sk_csr_kernel(const int32_t* bptr, const int32_t* bcol, int64_t n,
+                              int64_t* rowptr, int32_t* colind) {
+  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (J >= n) return;
+  const int64_t b0 = bptr[J];
+  const int nb = bptr[J + 1] - bptr[J];
+  for (int a = 0; a < NORB; ++a) {
+    const int64_t r0 = 16 * b0 + 4 * (int64_t)a * nb;
+    rowptr[NORB * J + a] = r0;
+    for (int t = 0; t < nb; ++t)
+      for (int be = 0; be < NORB; ++be) colind[r0 + 4 * t + be] = NORB * bcol[b0 + t] + be;
+  }
+  if (J == n - 1) rowptr[NORB * n] = 16 * (int64_t)bptr[n];
+}
+
+// ---------------------------------------------------------------------------
+// two-center blocks and their derivatives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void radial(const SKModelDev& m, double r, double& u, double& du) {
+  const double width = m.r_cut - m.r_on;
+  const double t = (r - m.r_on) / width;
+  double fc, dfc;
+  if (t <= 0.0) {
+    fc = 1.0;
+    dfc = 0.0;
+  } else if (t >= 1.0) {
+    fc = 0.0;
+    dfc = 0.0;
+  } else {
+    const double t2 = t * t, t3 = t2 * t;
+    fc = 1.0 - (10.0 * t3 - 15.0 * t3 * t + 6.0 * t3 * t2);
+    dfc = -(30.0 * t2 - 60.0 * t3 + 30.0 * t3 * t) / width;
+  }
+  const double g = (m.r0 / r) * (m.r0 / r);
+  const double dg = -2.0 * m.r0 * m.r0 / (r * r * r);
+  u = g * fc;
+  du = dg * fc + g * dfc;
+}
+
+// B (4x4) for displacement d from the row atom to the column atom
+__device__ __forceinline__ void two_center(const SKModelDev& m, const double* V, double dx,
+                                           double dy, double dz, double B[4][4]) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double l[3] = {dx / r, dy / r, dz / r};
+  double u, du;
+  radial(m, r, u, du);
+  B[0][0] = V[0] * u;
+  for (int a = 0; a < 3; ++a) {
+    B[0][1 + a] = l[a] * V[1] * u;
+    B[1 + a][0] = -l[a] * V[1] * u;
+    for (int b = 0; b < 3; ++b) {
+      const double ll = l[a] * l[b];
+      B[1 + a][1 + b] = (ll * V[2] + ((a == b ? 1.0 : 0.0) - ll) * V[3]) * u;
+    }
+  }
+}
+
+// sum_ab G[a][b] dB_ab/dd  (3-vector), for weights G on the block
+__device__ __forceinline__ void two_center_contract(const SKModelDev& m, const double* V,
+                                                    double dx, double dy, double dz,
+                                                    const double G[4][4], double out[3]) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double l[3] = {dx / r, dy / r, dz / r};
+  double u, du;
+  radial(m, r, u, du);
+  for (int c = 0; c < 3; ++c) {
+    const double dr = l[c];
+    double acc = G[0][0] * V[0] * du * dr;
+    for (int a = 0; a < 3; ++a) {
+      const double dla = ((a == c ? 1.0 : 0.0) - l[a] * l[c]) / r;
+      const double sp = dla * V[1] * u + l[a] * V[1] * du * dr;
+      acc += G[0][1 + a] * sp - G[1 + a][0] * sp;
+      for (int b = 0; b < 3; ++b) {
+        const double dlb = ((b == c ? 1.0 : 0.0) - l[b] * l[c]) / r;
+        const double ll = l[a] * l[b];
+        const double ang = ll * V[2] + ((a == b ? 1.0 : 0.0) - ll) * V[3];
+        const double dang = (dla * l[b] + l[a] * dlb) * (V[2] - V[3]);
+        acc += G[1 + a][1 + b] * (dang * u + ang * du * dr);
+      }
+    }
+    out[c] = acc;
+  }
+}
+
+__global__ void sk_values_kernel(SKModelDev m, const double* pos, int64_t n, Box box,
+                                 const int32_t* bptr, const int32_t* bcol, double* H, double* S) {
+  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (J >= n) return;
+  const int64_t b0 = bptr[J];
+  const int nb = bptr[J + 1] - bptr[J];
+  for (int t = 0; t < nb; ++t) {
+    const int K = bcol[b0 + t];
+    double Bh[4][4], Bs[4][4];
+    if (K == J) {
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          Bh[a][b] = (a == b) ? (a == 0 ? m.es : m.ep) : 0.0;
+          Bs[a][b] = (a == b) ? 1.0 : 0.0;
+        }
+    } else {
+      double dx = pos[3 * K] - pos[3 * J], dy = pos[3 * K + 1] - pos[3 * J + 1],
+             dz = pos[3 * K + 2] - pos[3 * J + 2];
+      min_image(box, dx, dy, dz);
+      two_center(m, m.vh, dx, dy, dz, Bh);
+      two_center(m, m.vs, dx, dy, dz, Bs);
+    }
+    for (int a = 0; a < 4; ++a) {
+      const int64_t r0 = 16 * b0 + 4 * (int64_t)a * nb + 4 * t;
+      for (int b = 0; b < 4; ++b) {
+        H[r0 + b] = Bh[a][b];
+        S[r0 + b] = Bs[a][b];
+      }
+    }
+  }
+}
+
+// grad[I] = sum over blocks (I,K) and (K,I) of g . d(block)/dR_I
+__global__ void sk_vjp_kernel(SKModelDev m, const double* pos, int64_t n, Box box,
+                              const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
+                              const double* gH, const double* gS, double sgn, double* grad) {
+  const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  const int64_t b0 = bptr[I];
+  const int nb = bptr[I + 1] - bptr[I];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int t = 0; t < nb; ++t) {
+    const int K = bcol[b0 + t];
+    if (K == I) continue;
+    double dx = pos[3 * K] - pos[3 * I], dy = pos[3 * K + 1] - pos[3 * I + 1],
+           dz = pos[3 * K + 2] - pos[3 * I + 2];
+    min_image(box, dx, dy, dz);
+    // block (I, K): depends on R_I through d = R_K - R_I  -> minus sign
+    {
+      double Gh[4][4], Gs[4][4];
+      for (int a = 0; a < 4; ++a) {
+        const int64_t r0 = 16 * b0 + 4 * (int64_t)a * nb + 4 * t;
+        for (int b = 0; b < 4; ++b) {
+          Gh[a][b] = gH[r0 + b];
+          Gs[a][b] = sgn * gS[r0 + b];
+        }
+      }
+      double oh[3], os[3];
+      two_center_contract(m, m.vh, dx, dy, dz, Gh, oh);
+      two_center_contract(m, m.vs, dx, dy, dz, Gs, os);
+      for (int c = 0; c < 3; ++c) acc[c] -= oh[c] + os[c];
+    }
+    // block (K, I) in row K: depends on R_I through d' = R_I - R_K = -d -> plus sign
+    {
+      const int bt = btrans[b0 + t];
+      const int64_t k0 = bptr[K];
+      const int nbk = bptr[K + 1] - bptr[K];
+      const int tt = (int)(bt - k0);
+      double Gh[4][4], Gs[4][4];
+      for (int a = 0; a < 4; ++a) {
+        const int64_t r0 = 16 * k0 + 4 * (int64_t)a * nbk + 4 * tt;
+        for (int b = 0; b < 4; ++b) {
+          Gh[a][b] = gH[r0 + b];
+          Gs[a][b] = sgn * gS[r0 + b];
+        }
+      }
+      double oh[3], os[3];
+      two_center_contract(m, m.vh, -dx, -dy, -dz, Gh, oh);
+      two_center_contract(m, m.vs, -dx, -dy, -dz, Gs, os);
+      for (int c = 0; c < 3; ++c) acc[c] += oh[c] + os[c];
+    }
+  }
+  for (int c = 0; c < 3; ++c) grad[3 * I + c] = acc[c];
+}
+
+hipError_t launch_sk_count(const double* pos, int64_t n, const double cell[3], double rc,
+                           const CellList& cl, int32_t* cnt, int32_t* err, hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  hipLaunchKernelGGL(sk_count_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, pos, n, box,
+                     rc * rc, view_of(cl), cnt, err);
+  return hipGetLastError();
+}
+hipError_t launch_sk_fill(const double* pos, int64_t n, const double cell[3], double rc,
+                          const CellList& cl, const int32_t* bptr, int32_t* bcol, hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  hipLaunchKernelGGL(sk_fill_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, pos, n, box,
+                     rc * rc, view_of(cl), bptr, bcol);
+  return hipGetLastError();
+}
+hipError_t launch_sk_csr(const int32_t* bptr, const int32_t* bcol, int64_t n, int64_t* rowptr,
+                         int32_t* colind, hipStream_t s) {
+  hipLaunchKernelGGL(sk_csr_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, bptr, bcol, n,
+                     rowptr, colind);
+  return hipGetLastError();
+}
+hipError_t launch_sk_values(const SKModelDev& m, const double* pos, int64_t n,
+                            const double cell[3], const int32_t* bptr, const int32_t* bcol,
+                            double* H, double* S, hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  hipLaunchKernelGGL(sk_values_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, m, pos, n,
+                     box, bptr, bcol, H, S);
+  return hipGetLastError();
+}
+hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
+                         const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
+                         const double* gH, const double* gS, double sign_gS, double* grad,
+                         hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  hipLaunchKernelGGL(sk_vjp_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, m, pos, n, box,
+                     bptr, bcol, btrans, gH, gS, sign_gS, grad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// clusters: atoms within r_c of each atom (inclusive), sorted by id
+// ---------------------------------------------------------------------------
+constexpr int CTPB = 256;
+constexpr int CSORT = 256;  // sort width (>= CLUSTER_MAX)
+
+__global__ __launch_bounds__(CTPB) void cluster_scan_kernel(const double* pos, int64_t n, Box box,
+                                                            double rc2, CellView cv,
+                                                            int32_t* tmp, int32_t* cnt,
+                                                            int32_t* err) {
+  __shared__ int32_t s_list[CSORT];
+  __shared__ int s_n;
+  const int64_t J = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  const double xj = pos[3 * J], yj = pos[3 * J + 1], zj = pos[3 * J + 2];
+  auto test = [&](int k) {
+    double dx = pos[3 * k] - xj, dy = pos[3 * k + 1] - yj, dz = pos[3 * k + 2] - zj;
+    min_image(box, dx, dy, dz);
+    if (dx * dx + dy * dy + dz * dz <= rc2) {
+      const int slot = atomicAdd(&s_n, 1);
+      if (slot < CSORT) s_list[slot] = k;
+    }
+  };
+  if (cv.brute) {
+    for (int64_t k = tid; k < n; k += CTPB) test((int)k);
+  } else {
+    const int cx = cell_coord(xj, box.L[0], cv.nc[0]);
+    const int cy = cell_coord(yj, box.L[1], cv.nc[1]);
+    const int cz = cell_coord(zj, box.L[2], cv.nc[2]);
+    for (int q = 0; q < 27; ++q) {
+      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+      const int x = (cx + dx + cv.nc[0]) % cv.nc[0];
+      const int y = (cy + dy + cv.nc[1]) % cv.nc[1];
+      const int z = (cz + dz + cv.nc[2]) % cv.nc[2];
+      const int c = (z * cv.nc[1] + y) * cv.nc[0] + x;
+      for (int a = cv.start[c] + tid; a < cv.start[c + 1]; a += CTPB) test(cv.atoms[a]);
+    }
+  }
+  __syncthreads();
+  const int total = s_n;
+  if (total > CLUSTER_MAX) {
+    if (tid == 0) {
+      atomicOr(err, (int)KERR_CAPACITY);
+      cnt[J] = 0;
+    }
+    return;
+  }
+  for (int a = total + tid; a < CSORT; a += CTPB) s_list[a] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort of CSORT keys
+  for (int k = 2; k <= CSORT; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int i = tid; i < CSORT; i += CTPB) {
+        const int p = i ^ jj;
+        if (p > i) {
+          const int a = s_list[i], b = s_list[p];
+          const bool asc = (i & k) == 0;
+          if ((a > b) == asc) {
+            s_list[i] = b;
+            s_list[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int a = tid; a < total; a += CTPB) tmp[J * (int64_t)CLUSTER_MAX + a] = s_list[a];
+  if (tid == 0) cnt[J] = total;
+}
+
+__global__ void cluster_compact_kernel(const int32_t* tmp, const int32_t* cnt, const int64_t* ptr,
+                                       int64_t n, int32_t* atoms) {
+  const int64_t J = blockIdx.x;
+  if (J >= n) return;
+  for (int a = threadIdx.x; a < cnt[J]; a += blockDim.x)
+    atoms[ptr[J] + a] = tmp[J * (int64_t)CLUSTER_MAX + a];
+}
+
+hipError_t launch_cluster_scan_cv(const double* pos, int64_t n, const double cell[3], double rc,
+                                  const CellList& cl, int32_t* tmp, int32_t* cnt, int32_t* err,
+                                  hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  hipLaunchKernelGGL(cluster_scan_kernel, dim3((unsigned)n), dim3(CTPB), 0, s, pos, n, box,
+                     rc * rc, view_of(cl), tmp, cnt, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_cluster_compact(const int32_t* tmp, const int32_t* cnt, const int64_t* ptr,
+                                  int64_t n, int32_t* atoms, hipStream_t s) {
+  hipLaunchKernelGGL(cluster_compact_kernel, dim3((unsigned)n), dim3(64), 0, s, tmp, cnt, ptr, n,
+                     atoms);
+  return hipGetLastError();
+}
+
+}  // namespace mag

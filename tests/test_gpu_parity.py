@@ -1,0 +1,217 @@
+"""GPU path vs the CPU oracle, element by element, on seeded synthetic cells.
+
+Bars (floating point): |d rho| <= 1e-10 on every pattern entry, |dE|/atom and
+|dA|/atom <= 1e-9 eV, |N_oracle(mu_gpu) - N_e| <= 1e-9 (mu itself is
+ill-conditioned in a gap), |dF| <= 1e-8 eV/A.  Integer outputs (pattern,
+clusters, Krylov dimensions) must match exactly.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_context, log, np_, oracle_solution, oracle_system
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-10
+E_TOL = 1e-9
+F_TOL = 1e-8
+
+
+@pytest.mark.parametrize("key", [1, "mini_vac"])
+def test_sk_matrices_match_oracle(key):
+    log(f"[sk] config {key}")
+    s, sysm = oracle_system(key)
+    ctx = gpu_context(s)
+    rowptr, colind, H, S = (np_(x) for x in ctx._csr)
+    np.testing.assert_array_equal(rowptr, sysm.H.indptr)
+    np.testing.assert_array_equal(colind, sysm.H.indices)
+    np.testing.assert_allclose(H, sysm.H.data, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(S, sysm.S.data, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("key", [2, "mini_void", 1])
+def test_clusters_match_oracle(key):
+    from oracle import neighbors
+    log(f"[clusters] config {key}")
+    s, _ = oracle_system(key)
+    ctx = gpu_context(s)
+    ptr, atoms = (np_(x) for x in ctx.get_clusters())
+    rptr, ratoms = neighbors.all_clusters(s.pos, s.cell, s.r_cluster)
+    np.testing.assert_array_equal(ptr, rptr)
+    np.testing.assert_array_equal(atoms, ratoms)
+
+
+def _compare_solution(key, workflow="recompute", schedule="auto"):
+    s, sysm = oracle_system(key)
+    ref = oracle_solution(key)
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow=workflow,
+                         schedule=schedule)
+    eps, w, nu_eff = (np_(x) for x in ctx.spectra())
+    log(f"[{key}] mu gpu {mu:.12f} oracle {ref.mu:.12f}  E {E:.10f} / {ref.E_band:.10f}")
+    np.testing.assert_array_equal(nu_eff, ref.cd["nu_eff"])
+    k = eps.shape[1]
+    np.testing.assert_allclose(eps, ref.cd["eps"][:, :k], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(w, ref.cd["w"][:, :k], rtol=0, atol=1e-10)
+    from oracle import fermi, solve
+    e_all, w_all = solve.valid_terms(ref.cd)
+    assert abs(fermi.electron_count(mu, e_all, w_all, s.kT) - s.n_electrons) < 1e-9
+    rho, pi = (np_(x) for x in ctx.density_matrix())
+    # the oracle's rho at the GPU's mu (mu is ill-conditioned inside a gap)
+    rho_o, pi_o = solve.density_on_pattern(sysm, ref.cd, mu)
+    drho = np.abs(rho - rho_o).max()
+    log(f"[{key}] max |d rho| {drho:.3e}, max |d pi| {np.abs(pi - pi_o).max():.3e}")
+    assert drho <= RHO_TOL
+    assert np.abs(pi - pi_o).max() <= 10 * RHO_TOL
+    E_o, A_o, _, _ = solve.energies(sysm, ref.cd, mu)
+    n = s.n_atoms
+    assert abs(E - E_o) / n <= E_TOL and abs(A - A_o) / n <= E_TOL
+    # energy through rho agrees with the spectral sum
+    assert abs(float(sysm.H.data @ rho) - E) <= 1e-9 * abs(E)
+    return ctx, s, sysm, ref
+
+
+def test_parity_config1_whole_cell():
+    log("[parity] config 1")
+    _compare_solution(1)
+
+
+def test_parity_vacancy_cell_full():
+    log("[parity] mini_vac")
+    _compare_solution("mini_vac")
+
+
+def test_parity_void_cell_full_store_workflow():
+    log("[parity] mini_void store")
+    _compare_solution("mini_void", workflow="store")
+
+
+def test_workflows_and_schedules_are_bitwise_equal():
+    log("[bitwise] mini_vac workflows and schedules")
+    s, _ = oracle_system("mini_vac")
+    ctx = gpu_context(s)
+    out = {}
+    for wf, sch in [("recompute", "persistent"), ("store", "grid"), ("recompute", "plain")]:
+        mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow=wf,
+                             schedule=sch)
+        eps, w, nu_eff = (np_(x) for x in ctx.spectra())
+        rho, pi = (np_(x) for x in ctx.density_matrix())
+        out[(wf, sch)] = (mu, E, A, eps, w, rho, pi)
+    base = out[("recompute", "persistent")]
+    for key, v in out.items():
+        for a, b in zip(base, v):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), key
+
+
+def test_forces_match_oracle_and_sum_to_zero():
+    log("[forces] mini_vac")
+    from oracle import solve
+    from paper_1210_1531_amd import model
+    s, sysm = oracle_system("mini_vac")
+    ref = oracle_solution("mini_vac")
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    F = np_(ctx.forces(model.sk_model()))
+    rho, pi = (np_(x) for x in ctx.density_matrix())
+    F_o = solve.forces(sysm, rho, pi)  # oracle contraction of the GPU's rho, pi
+    np.testing.assert_allclose(F, F_o, rtol=0, atol=F_TOL)
+    rho_o, pi_o = solve.density_on_pattern(sysm, ref.cd, mu)
+    F_full = solve.forces(sysm, rho_o, pi_o)  # fully oracle gradient at the same mu
+    log(f"[forces] max |dF| vs oracle {np.abs(F - F_full).max():.3e}")
+    np.testing.assert_allclose(F, F_full, rtol=0, atol=F_TOL)
+    assert np.abs(F.sum(axis=0)).max() < 1e-9
+
+
+def test_sampled_columns_at_full_size_config2():
+    # the benchmark workload: every column on the GPU, a sample of columns
+    # (largest, smallest and random clusters) recomputed one by one by the oracle
+    from oracle import krylov, neighbors
+    import gen
+    s = gen.make(2)
+    log(f"[config2] {s.n_atoms} atoms")
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    eps, w, nu_eff = (np_(x) for x in ctx.spectra())
+    rho, _ = (np_(x) for x in ctx.density_matrix())
+    rowptr = np_(ctx._csr[0])
+    colind = np_(ctx._csr[1])
+    ptr, atoms = (np_(x) for x in ctx.get_clusters())
+    sizes = np.diff(ptr)
+    rng = np.random.default_rng(7)
+    atoms_pick = np.unique(np.concatenate([np.argsort(sizes)[:3], np.argsort(sizes)[-3:],
+                                           rng.choice(s.n_atoms, 10, replace=False)]))
+    worst = 0.0
+    for J in atoms_pick:
+        clus = neighbors.cluster_of(s.pos, s.cell, int(J), s.r_cluster)
+        np.testing.assert_array_equal(clus, atoms[ptr[J]:ptr[J + 1]])
+        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
+        jl = int(np.searchsorted(clus, J))
+        for a in range(4):
+            j = 4 * int(J) + a
+            res = krylov.column_mode_k(Hc, Sc, 4 * jl + a, s.nu)
+            assert res.nu_eff == nu_eff[j]
+            np.testing.assert_allclose(eps[j, :res.nu_eff], res.eps, rtol=0, atol=1e-9)
+            np.testing.assert_allclose(w[j, :res.nu_eff], res.w, rtol=0, atol=1e-10)
+            col, _ = krylov.density_column(res, mu, s.kT)
+            lo, hi = rowptr[j], rowptr[j + 1]
+            rows = np.searchsorted(clus, colind[lo:hi] // 4) * 4 + colind[lo:hi] % 4
+            d = np.abs(rho[lo:hi] - col[rows]).max()
+            worst = max(worst, d)
+    log(f"[config2] sampled {len(atoms_pick)} atoms, max |d rho| {worst:.3e}")
+    assert worst <= RHO_TOL
+    # invariants at full size: closure of every column's weights, electron count
+    sums = np.where(np.arange(w.shape[1])[None, :] < nu_eff[:, None], w, 0.0).sum(axis=1)
+    np.testing.assert_allclose(sums, 2.0, atol=1e-11)
+    assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
+
+
+def test_green_and_cluster_columns_match_oracle():
+    from oracle import krylov, neighbors
+    import gen
+    s = gen.make("mini_vac")
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    cols = np.array([0, 5, 333, 4 * s.n_atoms - 1], dtype=np.int32)
+    z = np.array([0.3 + 0.5j, -4.0 + 0.05j, 12.0 + 1.0j])
+    G, off = ctx.green_columns(cols, z, nu=s.nu, kT=s.kT)
+    R, off2 = ctx.cluster_columns(cols)
+    R = np_(R)
+    np.testing.assert_array_equal(off, off2)
+    for i, j in enumerate(cols):
+        J = int(j) // 4
+        clus = neighbors.cluster_of(s.pos, s.cell, J, s.r_cluster)
+        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
+        res = krylov.column_mode_k(Hc, Sc, 4 * int(np.searchsorted(clus, J)) + int(j) % 4, s.nu)
+        g_ref = krylov.green_column(res, z)  # (n_C, nz)
+        n_c = off[i + 1] - off[i]
+        g = G[off[i] * z.size:off[i + 1] * z.size].reshape(z.size, n_c).T
+        np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-10)
+        rho_ref, _ = krylov.density_column(res, mu, s.kT)
+        np.testing.assert_allclose(R[off[i]:off[i + 1]], rho_ref, rtol=0, atol=RHO_TOL)
+
+
+def test_error_paths():
+    from paper_1210_1531_amd import MagError, _lib as L
+    import gen
+    s = gen.make(1)
+    ctx = gpu_context(s)
+    with pytest.raises(MagError) as e:
+        ctx.density_matrix()
+    assert e.value.status == L.MAG_ESTATE
+    with pytest.raises(MagError) as e:
+        ctx.solve(nu=s.nu, kT=s.kT, n_electrons=0.0)
+    assert e.value.status == L.MAG_EBRACKET
+    with pytest.raises(MagError) as e:
+        ctx.solve(nu=0, kT=s.kT, n_electrons=s.n_electrons)
+    assert e.value.status == L.MAG_EINVAL
+    rowptr, colind, H, S = (np_(x) for x in ctx._csr)
+    Hbad = H.copy()
+    Hbad[7] = np.nan
+    with pytest.raises(MagError) as e:
+        ctx.update_values(Hbad, S)
+    assert e.value.status == L.MAG_ENONFINITE
+    bad = colind.copy()
+    bad[0], bad[1] = bad[1], bad[0]
+    with pytest.raises(MagError) as e:
+        ctx.set_system(rowptr, bad, H, S, pos=s.pos, cell=s.cell, r_cluster=s.r_cluster)
+    assert e.value.status == L.MAG_EINVAL
