@@ -291,6 +291,11 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the context */
   int32_t bisect_levels;   /* halvings of the last bisection */
   int32_t schedule_used;   /* mag_schedule actually launched */
+  double t_krylov_ms;      /* last pass 1: summed durations of the Krylov kernel launches
+                              (HIP events on the context stream; 0 for PLAIN) */
+  double t_eig_ms;         /* last pass 1: summed durations of the eigensolver launches */
+  int32_t krylov_launches; /* Krylov kernel launches in the last pass 1 */
+  int32_t reserved;
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

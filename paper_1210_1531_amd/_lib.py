@@ -82,6 +82,10 @@ class MagStats(C.Structure):
         ("device_bytes", C.c_int64),
         ("bisect_levels", C.c_int32),
         ("schedule_used", C.c_int32),
+        ("t_krylov_ms", C.c_double),
+        ("t_eig_ms", C.c_double),
+        ("krylov_launches", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -130,6 +130,16 @@ bool whole_cell(const double cell[3], double rc) {
   return rc <= 0.0 || 2.0 * rc >= lmin;
 }
 
+// events from a per-context pool (created once, destroyed with the context)
+hipEvent_t pool_event(mag_ctx* ctx, size_t i) {
+  while (ctx->ev_pool.size() <= i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[i];
+}
+
 struct Timer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s;
@@ -214,6 +224,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
   int schedule = job.schedule == MAG_SCHED_AUTO ? MAG_SCHED_PERSISTENT : job.schedule;
   ctx->stats.schedule_used = schedule;
 
+  size_t timed = 0;
   int64_t i0 = 0;
   while (i0 < n) {
     // chunk: same rows-per-thread class, at most bsz slots
@@ -302,8 +313,20 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
         const int per_cu = occ ? std::max(1, std::atoi(occ)) : 2;
         grid = (int)std::min<int64_t>(cnt, (int64_t)ncu * per_cu);
       }
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+      if (ctx->time_kernels) {
+        e0 = pool_event(ctx, 3 * timed + 0);
+        e1 = pool_event(ctx, 3 * timed + 1);
+        e2 = pool_event(ctx, 3 * timed + 2);
+      }
+      if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
       HIPCHK(launch_krylov(ka, cap, cls, grid, ctx->stream));
+      if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
       HIPCHK(launch_eig(ea, ctx->stream));
+      if (e2) {
+        HIPCHK(hipEventRecord(e2, ctx->stream));
+        ++timed;
+      }
     }
 
     if (job.consumer == 2) {
@@ -333,6 +356,20 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
     }
     i0 = i1;
     if (i0 < n) TRY(sync(ctx));  // the next chunk reuses the scratch
+  }
+  if (ctx->time_kernels) {
+    TRY(sync(ctx));
+    double tk = 0.0, te = 0.0;
+    for (size_t q = 0; q < timed; ++q) {
+      float a = 0.f, b = 0.f;
+      HIPCHK(hipEventElapsedTime(&a, ctx->ev_pool[3 * q], ctx->ev_pool[3 * q + 1]));
+      HIPCHK(hipEventElapsedTime(&b, ctx->ev_pool[3 * q + 1], ctx->ev_pool[3 * q + 2]));
+      tk += a;
+      te += b;
+    }
+    ctx->stats.t_krylov_ms = tk;
+    ctx->stats.t_eig_ms = te;
+    ctx->stats.krylov_launches = (int32_t)timed;
   }
   return MAG_OK;
 }
@@ -452,6 +489,7 @@ void mag_destroy(mag_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   const bool own = ctx->own_stream;
   hipStream_t s = ctx->stream;
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;  // DevBuf destructors free device memory
   if (own && s) (void)hipStreamDestroy(s);
 }
@@ -855,7 +893,13 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
   job.nu_eff = ctx->nu_eff.as<int32_t>();
   job.want_P = store ? 1 : 0;
   job.P_store = store ? ctx->P.as<double>() : nullptr;
-  TRY(run_columns(ctx, job));
+  ctx->time_kernels = true;
+  ctx->stats.t_krylov_ms = 0.0;
+  ctx->stats.t_eig_ms = 0.0;
+  ctx->stats.krylov_launches = 0;
+  const int rc_pass1 = run_columns(ctx, job);
+  ctx->time_kernels = false;
+  TRY(rc_pass1);
   ctx->stats.t_pass1_ms = t1.stop_ms();
   TRY(take_errors(ctx, "pass 1"));
 

@@ -252,4 +252,7 @@ struct mag_ctx {
   mag::MuState h_state{};
 
   mag_stats stats{};
+  // per-launch timing events of the Krylov and eigensolver kernels (pass 1)
+  std::vector<hipEvent_t> ev_pool;
+  bool time_kernels = false;
 };

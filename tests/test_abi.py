@@ -53,6 +53,7 @@ int main(void) {
   P(mag_system, cell); P(mag_system, r_cluster); P(mag_system, clus_atoms);
   P(mag_opts, mu_fixed); P(mag_opts, workflow); P(mag_opts, schedule);
   P(mag_stats, n_columns); P(mag_stats, bisect_levels); P(mag_stats, schedule_used);
+  P(mag_stats, t_krylov_ms); P(mag_stats, krylov_launches);
   P(mag_sk_model, r_cut);
   return 0;
 }
