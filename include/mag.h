@@ -67,8 +67,14 @@ enum mag_mem { MAG_HOST = 0, MAG_DEVICE = 1 };
 /* Memory workflow of Eq. 3.  RECOMPUTE: pass 1 keeps only the spectral data
  * (eps, w) needed for mu and recomputes every Krylov column for rho in pass 2
  * (the letter's memory-saving workflow).  STORE: pass 1 also keeps Y d on the
- * pattern (n_pat x nu doubles per column) and pass 2 reads it back. */
-enum mag_workflow { MAG_WORKFLOW_RECOMPUTE = 0, MAG_WORKFLOW_STORE = 1 };
+ * pattern (n_pat x nu doubles per column) and pass 2 reads it back.  AUTO:
+ * STORE when that buffer (nnz x nu doubles) fits in min(16 GB, a quarter of
+ * the free device memory), RECOMPUTE otherwise. */
+enum mag_workflow {
+  MAG_WORKFLOW_RECOMPUTE = 0,
+  MAG_WORKFLOW_STORE = 1,
+  MAG_WORKFLOW_AUTO = 2
+};
 
 /* Launch schedule of the per-column Krylov kernels.  PERSISTENT: one launch of
  * resident workgroups pulling columns (largest clusters first) from a device
@@ -198,7 +204,7 @@ typedef struct {
 } mag_opts;
 
 /* Fill opts with the defaults (nu 30, kT 0.1, n_electrons 0 (must be set),
- * mu_tol 1e-12, mu_fixed NaN, breakdown 1e-12, RECOMPUTE, AUTO). */
+ * mu_tol 1e-12, mu_fixed NaN, breakdown 1e-12, workflow AUTO, schedule AUTO). */
 void mag_opts_default(mag_opts* opts);
 
 /* Pass 1 of Eq. 3 over every column, then mu, then the energies.
@@ -295,7 +301,7 @@ typedef struct {
                               (HIP events on the context stream; 0 for PLAIN) */
   double t_eig_ms;         /* last pass 1: summed durations of the eigensolver launches */
   int32_t krylov_launches; /* Krylov kernel launches in the last pass 1 */
-  int32_t reserved;
+  int32_t workflow_used;   /* mag_workflow of the last solve (never AUTO) */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

@@ -24,6 +24,7 @@ MAG_HOST = 0
 MAG_DEVICE = 1
 MAG_WORKFLOW_RECOMPUTE = 0
 MAG_WORKFLOW_STORE = 1
+MAG_WORKFLOW_AUTO = 2
 MAG_SCHED_AUTO = 0
 MAG_SCHED_PERSISTENT = 1
 MAG_SCHED_GRID = 2
@@ -85,7 +86,7 @@ class MagStats(C.Structure):
         ("t_krylov_ms", C.c_double),
         ("t_eig_ms", C.c_double),
         ("krylov_launches", C.c_int32),
-        ("reserved", C.c_int32),
+        ("workflow_used", C.c_int32),
     ]
 
 

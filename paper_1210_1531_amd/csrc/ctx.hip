@@ -189,14 +189,26 @@ struct ColumnJob {
   int nz = 0;
 };
 
-int rows_class(int atoms) {
-  const int nC = NORB * atoms;
-  const int t = krylov_threads();
-  return (nC + t - 1) / t;
+// split slots [0, n) of a column list into KRYLOV_QUEUES contiguous ranges of
+// about equal work (cluster size as the cost of a column)
+std::vector<int64_t> queue_ranges(const mag_ctx* ctx, const int32_t* cols, int64_t n) {
+  std::vector<int64_t> beg(KRYLOV_QUEUES + 1, n);
+  double total = 0.0;
+  for (int64_t i = 0; i < n; ++i) total += ctx->h_clus_size[cols[i] >> 2];
+  double acc = 0.0;
+  int q = 1;
+  beg[0] = 0;
+  for (int64_t i = 0; i < n && q < KRYLOV_QUEUES; ++i) {
+    acc += ctx->h_clus_size[cols[i] >> 2];
+    // cut after whole atoms only (the four columns of an atom stay together)
+    const bool atom_end = (i + 1 == n) || ((cols[i + 1] >> 2) != (cols[i] >> 2));
+    if (atom_end && acc >= total * q / KRYLOV_QUEUES) beg[q++] = i + 1;
+  }
+  for (; q <= KRYLOV_QUEUES; ++q) beg[q] = n;
+  return beg;
 }
 
-int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr) {
-  (void)slot_done_hook;
+int run_columns(mag_ctx* ctx, ColumnJob& job) {
   const int64_t n = (int64_t)job.cols_host.size();
   if (n == 0) return MAG_OK;
   const int cap = krylov_capacity(job.nu);
@@ -214,27 +226,24 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
   ALLOC(ctx->k_qpat, sizeof(double) * bsz * (size_t)pat_stride * cap);
   ALLOC(ctx->k_nu, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_npat, sizeof(int32_t) * bsz);
-  ALLOC(ctx->k_queue, sizeof(int32_t) * 4);
+  ALLOC(ctx->k_queue, sizeof(int32_t) * KRYLOV_QUEUES);
+  ALLOC(ctx->k_qbeg, sizeof(int64_t) * (KRYLOV_QUEUES + 1));
   double* Pbuf = job.P_store;
   if (job.want_P && !job.P_store) {
     ALLOC(ctx->tmp_out, sizeof(double) * bsz * (size_t)pat_stride * job.nu);
     Pbuf = ctx->tmp_out.as<double>();
   }
+  int maxat = 1;
+  for (int64_t i = 0; i < n; ++i) maxat = std::max(maxat, ctx->h_clus_size[job.cols_host[i] >> 2]);
+  if (NORB * maxat > krylov_rows(cap))
+    return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the Krylov kernel holds for this nu");
   const int ncu = device_count_cus(ctx->device);
   int schedule = job.schedule == MAG_SCHED_AUTO ? MAG_SCHED_PERSISTENT : job.schedule;
   ctx->stats.schedule_used = schedule;
 
   size_t timed = 0;
-  int64_t i0 = 0;
-  while (i0 < n) {
-    // chunk: same rows-per-thread class, at most bsz slots
-    const int J0 = job.cols_host[i0] >> 2;
-    const int cls = rows_class(ctx->h_clus_size[J0]);
-    int64_t i1 = i0 + 1;
-    while (i1 < n && i1 - i0 < bsz && rows_class(ctx->h_clus_size[job.cols_host[i1] >> 2]) == cls)
-      ++i1;
-    const int64_t cnt = i1 - i0;
-    if (cls > 3) return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the kernel supports");
+  for (int64_t i0 = 0; i0 < n; i0 += bsz) {
+    const int64_t cnt = std::min(bsz, n - i0);
 
     KrylovArgs ka{};
     ka.bptr = ctx->bptr.as<int32_t>();
@@ -245,6 +254,8 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
     ka.cols = job.cols_dev + i0;
     ka.ncols = cnt;
     ka.queue = nullptr;
+    ka.qbeg = nullptr;
+    ka.nqueue = 0;
     ka.nu = job.nu;
     ka.breakdown = job.breakdown;
     ka.hs = ctx->k_hs.as<double>();
@@ -287,7 +298,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
         k1.qpat = ka.qpat + q * (int64_t)pat_stride * cap;
         k1.nu_eff = ka.nu_eff + q;
         k1.npat = ka.npat + q;
-        HIPCHK(launch_krylov(k1, cap, cls, 1, ctx->stream));
+        HIPCHK(launch_krylov(k1, cap, 1, ctx->stream));
         EigArgs e1 = ea;
         e1.hs = k1.hs;
         e1.urow = k1.urow;
@@ -307,11 +318,17 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
     } else {
       int grid = (int)cnt;
       if (schedule == MAG_SCHED_PERSISTENT) {
-        HIPCHK(launch_fill_i32(ctx->k_queue.as<int32_t>(), 1, 0, ctx->stream));
+        const std::vector<int64_t> qb = queue_ranges(ctx, job.cols_host.data() + i0, cnt);
+        HIPCHK(hipMemcpyAsync(ctx->k_qbeg.p, qb.data(), sizeof(int64_t) * qb.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(launch_fill_i32(ctx->k_queue.as<int32_t>(), KRYLOV_QUEUES, 0, ctx->stream));
         ka.queue = ctx->k_queue.as<int32_t>();
+        ka.qbeg = ctx->k_qbeg.as<int64_t>();
+        ka.nqueue = KRYLOV_QUEUES;
         const char* occ = std::getenv("MAG_PERSIST_PER_CU");
-        const int per_cu = occ ? std::max(1, std::atoi(occ)) : 2;
+        const int per_cu = occ ? std::max(1, std::atoi(occ)) : 1;
         grid = (int)std::min<int64_t>(cnt, (int64_t)ncu * per_cu);
+        TRY(sync(ctx));  // the host range vector goes out of scope
       }
       hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
       if (ctx->time_kernels) {
@@ -320,7 +337,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
         e2 = pool_event(ctx, 3 * timed + 2);
       }
       if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
-      HIPCHK(launch_krylov(ka, cap, cls, grid, ctx->stream));
+      HIPCHK(launch_krylov(ka, cap, grid, ctx->stream));
       if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
       HIPCHK(launch_eig(ea, ctx->stream));
       if (e2) {
@@ -354,8 +371,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, int64_t* slot_done_hook = nullptr)
       da.pi = job.pi;
       HIPCHK(launch_density(da, ctx->stream));
     }
-    i0 = i1;
-    if (i0 < n) TRY(sync(ctx));  // the next chunk reuses the scratch
+    if (i0 + cnt < n) TRY(sync(ctx));  // the next chunk reuses the scratch
   }
   if (ctx->time_kernels) {
     TRY(sync(ctx));
@@ -379,7 +395,8 @@ int check_opts(mag_ctx* ctx, const mag_opts* o) {
   if (o->nu < 1 || o->nu > NU_MAX)
     return fail(ctx, MAG_EINVAL, "nu must be in 1.." + std::to_string(NU_MAX));
   if (!(o->kT > 0.0) || !std::isfinite(o->kT)) return fail(ctx, MAG_EINVAL, "kT must be > 0");
-  if (o->workflow != MAG_WORKFLOW_RECOMPUTE && o->workflow != MAG_WORKFLOW_STORE)
+  if (o->workflow != MAG_WORKFLOW_RECOMPUTE && o->workflow != MAG_WORKFLOW_STORE &&
+      o->workflow != MAG_WORKFLOW_AUTO)
     return fail(ctx, MAG_EINVAL, "unknown workflow");
   if (o->schedule < MAG_SCHED_AUTO || o->schedule > MAG_SCHED_PLAIN)
     return fail(ctx, MAG_EINVAL, "unknown schedule");
@@ -502,7 +519,7 @@ void mag_opts_default(mag_opts* o) {
   o->mu_tol = 1e-12;
   o->mu_fixed = std::nan("");
   o->breakdown = 1e-12;
-  o->workflow = MAG_WORKFLOW_RECOMPUTE;
+  o->workflow = MAG_WORKFLOW_AUTO;
   o->schedule = MAG_SCHED_AUTO;
 }
 
@@ -801,12 +818,48 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
     ctx->sum_cluster_nnz = std::accumulate(hn.begin(), hn.end(), (int64_t)0);
   }
 
-  // column order: largest clusters first (ties by column id)
+  // column order: atoms along a Morton curve of their positions (spatially
+  // compact work queues), the four columns of an atom together
   std::vector<int32_t> atoms(N);
   std::iota(atoms.begin(), atoms.end(), 0);
-  std::stable_sort(atoms.begin(), atoms.end(), [&](int32_t a, int32_t b) {
-    return ctx->h_clus_size[a] > ctx->h_clus_size[b];
-  });
+  if (sys->pos && mem_kind == MAG_HOST) {
+    const double* p = sys->pos;
+    std::vector<uint64_t> key(N);
+    for (int64_t i = 0; i < N; ++i) {
+      uint64_t code = 0;
+      uint32_t c[3];
+      for (int d = 0; d < 3; ++d) {
+        double f = sys->cell[d] > 0 ? p[3 * i + d] / sys->cell[d] : 0.0;
+        f -= std::floor(f);
+        c[d] = (uint32_t)std::min(1023.0, std::max(0.0, f * 1024.0));
+      }
+      for (int b = 9; b >= 0; --b)
+        for (int d = 0; d < 3; ++d) code = (code << 1) | ((c[d] >> b) & 1u);
+      key[i] = code;
+    }
+    std::stable_sort(atoms.begin(), atoms.end(),
+                     [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  } else if (ctx->has_pos) {
+    std::vector<double> hp(3 * N);
+    HIPCHK(hipMemcpyAsync(hp.data(), ctx->pos.p, sizeof(double) * 3 * N, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    TRY(sync(ctx));
+    std::vector<uint64_t> key(N);
+    for (int64_t i = 0; i < N; ++i) {
+      uint64_t code = 0;
+      uint32_t c[3];
+      for (int d = 0; d < 3; ++d) {
+        double f = sys->cell[d] > 0 ? hp[3 * i + d] / sys->cell[d] : 0.0;
+        f -= std::floor(f);
+        c[d] = (uint32_t)std::min(1023.0, std::max(0.0, f * 1024.0));
+      }
+      for (int b = 9; b >= 0; --b)
+        for (int d = 0; d < 3; ++d) code = (code << 1) | ((c[d] >> b) & 1u);
+      key[i] = code;
+    }
+    std::stable_sort(atoms.begin(), atoms.end(),
+                     [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  }
   ctx->h_order.resize(M);
   for (int64_t i = 0; i < N; ++i)
     for (int a = 0; a < NORB; ++a) ctx->h_order[NORB * i + a] = NORB * atoms[i] + a;
@@ -871,13 +924,22 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
   ctx->solved = false;
   ctx->density_ready = false;
   ctx->opts = *opts;
+  if (opts->workflow == MAG_WORKFLOW_AUTO) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const double need = 8.0 * (double)ctx->nnz * opts->nu;
+    const double held = ctx->P.p ? (double)ctx->P.bytes : 0.0;  // reusable
+    const double limit = std::min(16e9, 0.25 * ((double)free_b + held));
+    ctx->opts.workflow = need <= limit ? MAG_WORKFLOW_STORE : MAG_WORKFLOW_RECOMPUTE;
+  }
+  ctx->stats.workflow_used = ctx->opts.workflow;
   const int nu = opts->nu;
   ctx->nu = nu;
   const int64_t M = ctx->M;
   ALLOC(ctx->eps, sizeof(double) * M * nu);
   ALLOC(ctx->w, sizeof(double) * M * nu);
   ALLOC(ctx->nu_eff, sizeof(int32_t) * M);
-  const bool store = opts->workflow == MAG_WORKFLOW_STORE;
+  const bool store = ctx->opts.workflow == MAG_WORKFLOW_STORE;
   if (store) ALLOC(ctx->P, sizeof(double) * ctx->nnz * nu);
 
   // ---- pass 1

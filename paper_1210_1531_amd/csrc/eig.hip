@@ -17,6 +17,7 @@
 namespace mag {
 
 constexpr int ETPB = 64;
+constexpr int MAXP = NU_MAX / 2;  // rotations per round at most
 
 __device__ __forceinline__ double wave_sum64(double x) {
 #pragma unroll
@@ -30,9 +31,11 @@ __device__ __forceinline__ void round_robin(int m, int r, int p, int& i, int& j)
     i = m - 1;
     j = r;
   } else {
-    const int mm = m - 1;
-    i = (r + p) % mm;
-    j = (r - p + mm) % mm;
+    const int mm = m - 1;  // r, p < mm, so one conditional subtraction wraps
+    i = r + p;
+    i -= (i >= mm) ? mm : 0;
+    j = r - p + mm;
+    j -= (j >= mm) ? mm : 0;
   }
   if (i > j) {
     const int t = i;
@@ -60,36 +63,42 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
     if (lane == 0) a.nu_eff_out[oi] = 0;
     return;
   }
-  const int m = n + (n & 1);
+  const int m = n + (n & 1);  // even size; an odd n gets one decoupled dummy index
   const int ld = m + 1;
+  const int half = m / 2;
   double* A = sm;                 // m x ld
   double* V = A + m * ld;         // m x ld
   double* L = V + m * ld;         // m x ld
-  double* rc = L + m * ld;        // m/2 cosines
-  double* rs = rc + 32;           // m/2 sines
-  double* ev = rs + 32;           // eigenvalues (m)
-  double* dv = ev + 64;           // d (m)
-  double* gv = dv + 64;           // g (m)
-  int* ri = reinterpret_cast<int*>(gv + 64);
-  int* rj = ri + 32;
-  int* perm = rj + 32;            // perm[rank] = eigen index
+  double2* rot = reinterpret_cast<double2*>(L + m * ld);  // (c, s) per pair, MAXP
+  double* ev = reinterpret_cast<double*>(rot + MAXP);      // eigenvalues (64)
+  double* dv = ev + 64;           // d (64)
+  double* gv = dv + 64;           // g (64)
+  double* uu = gv + 64;           // row l of Q (64)
+  double* s0 = uu + 64;           // first row of s (64)
+  int2* pij = reinterpret_cast<int2*>(s0 + 64);  // (i, j) per pair, MAXP
+  int* perm = reinterpret_cast<int*>(pij + MAXP); // perm[rank] = eigen index (64)
   int* flag = perm + 64;
+  int2* btab = reinterpret_cast<int2*>(flag + 4);  // (p, q) of each 2x2 block
 
   const double* h = a.hs + slot * (int64_t)(2 * cap * cap);
   const double* s = h + cap * cap;
 
   for (int idx = lane; idx < m * m; idx += ETPB) {
-    const int i = idx / m, k = idx % m;
+    const int i = idx / m, k = idx - (idx / m) * m;
     double hv = 0.0, sv = 0.0;
     if (i < n && k < n) {
       const int lo = min(i, k), hi = max(i, k);
       hv = h[(int64_t)hi * cap + lo];
       sv = s[(int64_t)hi * cap + lo];
     } else if (i == k) {
-      sv = 1.0;  // dummy index of odd n: identity overlap, zero h
+      sv = 1.0;  // dummy index: identity overlap, zero h
     }
     A[i * ld + k] = hv;
     L[i * ld + k] = sv;
+  }
+  if (lane < 64) {
+    uu[lane] = (lane < n) ? a.urow[slot * (int64_t)cap + lane] : 0.0;
+    s0[lane] = (lane < n) ? s[(int64_t)lane * cap + 0] : 0.0;  // s_{0 i} = s_{i 0}
   }
   if (lane == 0) flag[0] = 0;
   __syncthreads();
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
   }
   __syncthreads();
   for (int idx = lane; idx < m * m; idx += ETPB) {
-    const int i = idx / m, k = idx % m;
+    const int i = idx / m, k = idx - (idx / m) * m;
     if (i < k) {
       const double v = 0.5 * (A[i * ld + k] + A[k * ld + i]);
       A[i * ld + k] = v;
@@ -145,19 +154,35 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
   }
   __syncthreads();
 
-  // ---- cyclic Jacobi, round-robin ordering
-  const int half = m / 2;
+  // ---- cyclic Jacobi with round-robin pairs; each round applies A <- J^T A J
+  // by 2x2 blocks: block (p, q) of rows {i_p, j_p} and columns {i_q, j_q}
+  // becomes R_p^T B R_q, so every block is read and written by one lane.
+  const int nblk = half * (half + 1) / 2;  // blocks with p <= q
+  for (int b = lane; b < nblk; b += ETPB) {  // static block table (p, q)
+    int p = 0, rem = b;
+    while (rem >= half - p) {
+      rem -= half - p;
+      ++p;
+    }
+    btab[b] = make_int2(p, p + rem);
+  }
+  // V rows: lane l updates row (l mod rows_span) for pairs p = l / rows_span + k * groups
+  const int span = m <= 32 ? 32 : 64;
+  const int vrow = lane & (span - 1);
+  const int vgrp = lane / span;          // 0 or 1
+  const int groups = ETPB / span;        // 2 or 1
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int idx = lane; idx < m * m; idx += ETPB) {
-      const int i = idx / m, k = idx % m;
-      const double v = A[i * ld + k];
-      tot += v * v;
-      if (i != k) off += v * v;
+    if (lane < m) {
+      for (int i = 0; i < m; ++i) {
+        const double v = A[i * ld + lane];
+        tot += v * v;
+        off += (i != lane) ? v * v : 0.0;
+      }
     }
     off = wave_sum64(off);
     tot = wave_sum64(tot);
-    if (!(off > 1e-30 * tot) || m < 2) break;
+    if (!(off > 1e-30 * tot)) break;
     for (int r = 0; r < m - 1; ++r) {
       if (lane < half) {
         int i, jj;
@@ -172,34 +197,42 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
           c = 1.0 / sqrt(1.0 + t * t);
           sn = t * c;
         }
-        rc[lane] = c;
-        rs[lane] = sn;
-        ri[lane] = i;
-        rj[lane] = jj;
+        rot[lane] = make_double2(c, sn);
+        pij[lane] = make_int2(i, jj);
       }
       __syncthreads();
-      // rows: A <- J^T A  (lane owns column l)
-      for (int l = lane; l < m; l += ETPB) {
-        for (int p = 0; p < half; ++p) {
-          const int i = ri[p], jj = rj[p];
-          const double c = rc[p], sn = rs[p];
-          const double x = A[i * ld + l], y = A[jj * ld + l];
-          A[i * ld + l] = c * x - sn * y;
-          A[jj * ld + l] = sn * x + c * y;
+      for (int b = lane; b < nblk; b += ETPB) {
+        const int2 pq = btab[b];
+        const int2 P = pij[pq.x], Q = pij[pq.y];
+        const double2 rp = rot[pq.x], rq = rot[pq.y];
+        const double x00 = A[P.x * ld + Q.x], x01 = A[P.x * ld + Q.y];
+        const double x10 = A[P.y * ld + Q.x], x11 = A[P.y * ld + Q.y];
+        // rows: new row i = c row_i - s row_j, new row j = s row_i + c row_j
+        const double y00 = rp.x * x00 - rp.y * x10, y01 = rp.x * x01 - rp.y * x11;
+        const double y10 = rp.y * x00 + rp.x * x10, y11 = rp.y * x01 + rp.x * x11;
+        // columns: new col i = c col_i - s col_j, new col j = s col_i + c col_j
+        const double z00 = rq.x * y00 - rq.y * y01, z01 = rq.y * y00 + rq.x * y01;
+        const double z10 = rq.x * y10 - rq.y * y11, z11 = rq.y * y10 + rq.x * y11;
+        A[P.x * ld + Q.x] = z00;
+        A[P.x * ld + Q.y] = z01;
+        A[P.y * ld + Q.x] = z10;
+        A[P.y * ld + Q.y] = z11;
+        if (pq.x != pq.y) {
+          A[Q.x * ld + P.x] = z00;
+          A[Q.y * ld + P.x] = z01;
+          A[Q.x * ld + P.y] = z10;
+          A[Q.y * ld + P.y] = z11;
         }
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J  (lane owns row l)
-      for (int l = lane; l < m; l += ETPB) {
-        for (int p = 0; p < half; ++p) {
-          const int i = ri[p], jj = rj[p];
-          const double c = rc[p], sn = rs[p];
-          const double x = A[l * ld + i], y = A[l * ld + jj];
-          A[l * ld + i] = c * x - sn * y;
-          A[l * ld + jj] = sn * x + c * y;
-          const double vx = V[l * ld + i], vy = V[l * ld + jj];
-          V[l * ld + i] = c * vx - sn * vy;
-          V[l * ld + jj] = sn * vx + c * vy;
+      // V <- V J
+      if (vrow < m) {
+        double* vr = V + vrow * ld;
+        for (int p = vgrp; p < half; p += groups) {
+          const int2 P = pij[p];
+          const double2 rp = rot[p];
+          const double x = vr[P.x], y = vr[P.y];
+          vr[P.x] = rp.x * x - rp.y * y;
+          vr[P.y] = rp.y * x + rp.x * y;
         }
       }
       __syncthreads();
@@ -229,14 +262,12 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
   __syncthreads();
 
   // ---- d = c^T u, g = c^T s e_1, w = 2 d g
-  const double* u = a.urow + slot * (int64_t)cap;
   for (int k = lane; k < n; k += ETPB) {
     double d = 0.0, g = 0.0;
     for (int i = 0; i < n; ++i) {
       const double cik = A[i * ld + k];
-      d = fma(u[i], cik, d);
-      const double s0i = s[(int64_t)i * cap + 0];  // s_{0 i} = s_{i 0}
-      g = fma(s0i, cik, g);
+      d = fma(uu[i], cik, d);
+      g = fma(s0[i], cik, g);
     }
     dv[k] = d;
     gv[k] = g;
@@ -260,16 +291,15 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
     const int np = a.npat[slot];
     const int64_t base = a.pmode ? a.rowptr[j] : slot * (int64_t)a.pat_stride;
     const double* qp = a.qpat + slot * (int64_t)a.pat_stride * cap;
-    for (int p = 0; p < np; ++p) {
-      const double* qrow = qp + (int64_t)p * cap;
-      for (int rk = lane; rk < nuo; rk += ETPB) {
+    for (int rk = lane; rk < nuo; rk += ETPB) {
+      const int k = rk < n ? perm[rk] : 0;
+      const double dk = rk < n ? dv[k] : 0.0;
+      for (int p = 0; p < np; ++p) {
+        const double* qrow = qp + (int64_t)p * cap;
         double y = 0.0;
-        if (rk < n) {
-          const int k = perm[rk];
+        if (rk < n)
           for (int i = 0; i < n; ++i) y = fma(qrow[i], A[i * ld + k], y);
-          y *= dv[k];
-        }
-        a.P[(base + p) * nuo + rk] = y;
+        a.P[(base + p) * nuo + rk] = y * dk;
       }
     }
   }
@@ -278,8 +308,9 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
 hipError_t launch_eig(const EigArgs& a, hipStream_t s) {
   if (a.ncols <= 0) return hipSuccess;
   const int m = a.nu + (a.nu & 1);
-  const size_t lds = (size_t)3 * m * (m + 1) * sizeof(double) + (32 + 32 + 64 * 3) * sizeof(double) +
-                     (32 + 32 + 64 + 4) * sizeof(int);
+  const size_t lds = (size_t)3 * m * (m + 1) * sizeof(double) + MAXP * sizeof(double2) +
+                     5 * 64 * sizeof(double) + MAXP * sizeof(int2) + (64 + 4) * sizeof(int) +
+                     (MAXP * (MAXP + 1) / 2) * sizeof(int2);
   hipLaunchKernelGGL(eig_kernel, dim3((unsigned)a.ncols), dim3(ETPB), lds, s, a);
   return hipGetLastError();
 }

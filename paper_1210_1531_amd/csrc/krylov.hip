@@ -1,11 +1,11 @@
 // Per-column Krylov growth and projection (hot path of the multiple Arnoldi
 // method: one Krylov subspace per column j of G = (zS - H)^-1, Eq. 1).
 //
-// One workgroup of 256 threads (4 waves) owns one column j = (J, alpha) at a
-// time.  Its cluster C(J) is gathered in LDS as a local block-CSR over the
-// global 4x4-block matrices (prologue), then nu Krylov steps run with the
-// basis Q (n_C x nu) distributed over the registers of the workgroup: thread t
-// owns cluster rows t, t + 256, t + 512.  Each step:
+// One workgroup of 512 threads (8 waves, two per SIMD) owns one column
+// j = (J, alpha) at a time.  Its cluster C(J) is gathered in LDS as a local
+// block-CSR over the global 4x4-block matrices (prologue), then nu Krylov
+// steps run with the basis Q (n_C x nu) distributed over the registers of the
+// workgroup: thread t owns cluster rows t and t + 512.  Each step:
 //   w = H_C q_k, z = S_C q_k       one fused SpMV (shared pattern and gathers)
 //   h[:,k] = Q^T w, s[:,k] = Q^T z  projection, taken from the first
 //                                   Gram-Schmidt pass's dot products
@@ -16,45 +16,18 @@
 // projected pencil (h, s) has the same Ritz pairs.  Dot products are reduced
 // with a deterministic wave reduce-scatter plus a fixed-order cross-wave sum,
 // so a column's result does not depend on which workgroup computes it.
+//
+// Scheduling: persistent workgroups pull columns from KRYLOV_QUEUES device
+// queues, each a spatially compact range of atoms; workgroup w starts on
+// queue w % KRYLOV_QUEUES (workgroups are dealt to the XCDs round-robin, so a
+// queue's clusters share that XCD's L2) and steals from the others when its
+// own is empty.
 #include "mag_internal.h"
+#include "wave.h"
 
 namespace mag {
 
-constexpr int KTPB = 256;
-constexpr int KWAVES = KTPB / 64;
-constexpr int ENT_MAX = CLUSTER_MAX * 28;  // local blocks of a cluster (average row <= 28)
-
-// Sum NV = 2^LOG per-lane values over the wave.  Afterwards lane l holds the
-// total of value index (l >> (6 - LOG)).  Deterministic for a fixed layout.
-template <int LOG>
-__device__ __forceinline__ double wave_reduce_scatter(double* v, int lane) {
-#pragma unroll
-  for (int step = 0; step < LOG; ++step) {
-    const int off = 32 >> step;
-    const bool up = (lane & off) != 0;
-    constexpr int dummy = 0;
-    (void)dummy;
-    const int half = (1 << LOG) >> (step + 1);
-#pragma unroll
-    for (int t = 0; t < (1 << LOG) / 2; ++t) {
-      if (t < half) {
-        const double keep = up ? v[t + half] : v[t];
-        const double send = up ? v[t] : v[t + half];
-        v[t] = keep + __shfl_xor(send, off);
-      }
-    }
-  }
-  double x = v[0];
-#pragma unroll
-  for (int off = 32 >> LOG; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
+constexpr int ENT_MAX = CLUSTER_MAX * 24;  // local blocks of a cluster
 
 __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   int lo = 0, hi = n - 1;
@@ -68,14 +41,14 @@ __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   return -1;
 }
 
-template <int NU, int R>
+template <int NU, int R, int KTPB>
 __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
+  constexpr int KWAVES = KTPB / 64;
   constexpr int NCH = (NU + 7) / 8;
   constexpr int RED = 16 * NCH + 8;
   __shared__ int32_t s_atoms[CLUSTER_MAX];
   __shared__ int32_t s_lptr[CLUSTER_MAX + 1];
-  __shared__ int32_t s_lblk[ENT_MAX];
-  __shared__ int16_t s_lcol[ENT_MAX];
+  __shared__ uint2 s_ent[ENT_MAX];  // (global block, local column atom)
   __shared__ int16_t s_pat[NC_MAX];
   __shared__ double s_x[NC_MAX];
   __shared__ double s_red[KWAVES][RED];
@@ -86,14 +59,29 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int cap = a.cap;
+  int q = a.queue ? (int)(blockIdx.x % (unsigned)a.nqueue) : 0;
+  int tried = 0;
 
   for (int64_t it = 0;; ++it) {
     int64_t slot;
     if (a.queue) {
-      if (tid == 0) s_misc[0] = atomicAdd(a.queue, 1);
+      if (tid == 0) {
+        int64_t sl = -1;
+        while (tried < a.nqueue) {
+          const int64_t cand = a.qbeg[q] + atomicAdd(&a.queue[q], 1);
+          if (cand < a.qbeg[q + 1]) {
+            sl = cand;
+            break;
+          }
+          q = (q + 1) % a.nqueue;
+          ++tried;
+        }
+        s_misc[0] = (int)sl;
+      }
       __syncthreads();
       slot = s_misc[0];
       __syncthreads();
+      if (slot < 0) break;
     } else {
       if (it > 0) break;
       slot = blockIdx.x;
@@ -154,8 +142,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       for (int b = a.bptr[I]; b < a.bptr[I + 1]; ++b) {
         const int kl = lds_find(s_atoms, nat, a.bcol[b]);
         if (kl >= 0) {
-          s_lblk[e] = b;
-          s_lcol[e] = (int16_t)kl;
+          s_ent[e] = make_uint2((unsigned)b, (unsigned)kl);
           ++e;
         }
       }
@@ -163,18 +150,31 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     __syncthreads();
     // pattern rows of column j: block row of J, in CSR order (block t, orbital)
     for (int t = tid; t < NORB * nbJ; t += KTPB) {
-      const int kl = s_lcol[s_lptr[jl] + (t >> 2)];
+      const int kl = (int)s_ent[s_lptr[jl] + (t >> 2)].y;
       s_pat[NORB * kl + (t & 3)] = (int16_t)t;
     }
     const int ell = NORB * jl + alpha;
     for (int i = tid; i < nC; i += KTPB) s_x[i] = (i == ell) ? 1.0 : 0.0;
 
-    double q[R][NU];
+    double qv[R][NU];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
 #pragma unroll
-      for (int i = 0; i < NU; ++i) q[rr][i] = 0.0;
-      if (tid + KTPB * rr == ell) q[rr][0] = 1.0;
+      for (int i = 0; i < NU; ++i) qv[rr][i] = 0.0;
+      if (tid + KTPB * rr == ell) qv[rr][0] = 1.0;
+    }
+    // row bookkeeping of this thread
+    int e_beg[R], e_end[R], r_off[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int r = tid + KTPB * rr;
+      e_beg[rr] = 0;
+      e_end[rr] = 0;
+      r_off[rr] = (r & 3) * 4;
+      if (r < nC) {
+        e_beg[rr] = s_lptr[r >> 2];
+        e_end[rr] = s_lptr[(r >> 2) + 1];
+      }
     }
     const int nu_max = min(a.nu, nC);
     int nu_eff = nu_max;
@@ -183,37 +183,68 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     __syncthreads();
 
     for (int k = 0; k < nu_max; ++k) {
-      // ---- fused SpMV: w = H_C q_k, z = S_C q_k
+      // ---- fused SpMV: w = H_C q_k, z = S_C q_k (two blocks per iteration)
       double w[R], z[R];
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
-        const int r = tid + KTPB * rr;
-        double wa = 0.0, za = 0.0;
-        if (r < nC) {
-          const int il = r >> 2;
-          const int ro = (r & 3) * 4;
-          const int e1 = s_lptr[il + 1];
-          for (int e = s_lptr[il]; e < e1; ++e) {
-            const double* blk = a.bval + (int64_t)s_lblk[e] * 32 + ro;
-            const double2 h01 = *reinterpret_cast<const double2*>(blk);
-            const double2 h23 = *reinterpret_cast<const double2*>(blk + 2);
-            const double2 s01 = *reinterpret_cast<const double2*>(blk + 16);
-            const double2 s23 = *reinterpret_cast<const double2*>(blk + 18);
-            const double* xv = s_x + NORB * s_lcol[e];
-            const double2 x01 = *reinterpret_cast<const double2*>(xv);
-            const double2 x23 = *reinterpret_cast<const double2*>(xv + 2);
-            wa = fma(h01.x, x01.x, wa);
-            wa = fma(h01.y, x01.y, wa);
-            wa = fma(h23.x, x23.x, wa);
-            wa = fma(h23.y, x23.y, wa);
-            za = fma(s01.x, x01.x, za);
-            za = fma(s01.y, x01.y, za);
-            za = fma(s23.x, x23.x, za);
-            za = fma(s23.y, x23.y, za);
-          }
+        double wa = 0.0, za = 0.0, wb = 0.0, zb = 0.0;
+        const int ro = r_off[rr];
+        int e = e_beg[rr];
+        const int e1 = e_end[rr];
+        for (; e + 1 < e1; e += 2) {
+          const uint2 p0 = s_ent[e];
+          const uint2 p1 = s_ent[e + 1];
+          const double* b0 = a.bval + (int64_t)p0.x * 32 + ro;
+          const double* b1 = a.bval + (int64_t)p1.x * 32 + ro;
+          const double2 h01 = *reinterpret_cast<const double2*>(b0);
+          const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
+          const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
+          const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
+          const double2 g01 = *reinterpret_cast<const double2*>(b1);
+          const double2 g23 = *reinterpret_cast<const double2*>(b1 + 2);
+          const double2 t01 = *reinterpret_cast<const double2*>(b1 + 16);
+          const double2 t23 = *reinterpret_cast<const double2*>(b1 + 18);
+          const double2 x01 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y);
+          const double2 x23 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y + 2);
+          const double2 y01 = *reinterpret_cast<const double2*>(s_x + NORB * p1.y);
+          const double2 y23 = *reinterpret_cast<const double2*>(s_x + NORB * p1.y + 2);
+          wa = fma(h01.x, x01.x, wa);
+          wa = fma(h01.y, x01.y, wa);
+          wa = fma(h23.x, x23.x, wa);
+          wa = fma(h23.y, x23.y, wa);
+          za = fma(s01.x, x01.x, za);
+          za = fma(s01.y, x01.y, za);
+          za = fma(s23.x, x23.x, za);
+          za = fma(s23.y, x23.y, za);
+          wb = fma(g01.x, y01.x, wb);
+          wb = fma(g01.y, y01.y, wb);
+          wb = fma(g23.x, y23.x, wb);
+          wb = fma(g23.y, y23.y, wb);
+          zb = fma(t01.x, y01.x, zb);
+          zb = fma(t01.y, y01.y, zb);
+          zb = fma(t23.x, y23.x, zb);
+          zb = fma(t23.y, y23.y, zb);
         }
-        w[rr] = wa;
-        z[rr] = za;
+        if (e < e1) {
+          const uint2 p0 = s_ent[e];
+          const double* b0 = a.bval + (int64_t)p0.x * 32 + ro;
+          const double2 h01 = *reinterpret_cast<const double2*>(b0);
+          const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
+          const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
+          const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
+          const double2 x01 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y);
+          const double2 x23 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y + 2);
+          wa = fma(h01.x, x01.x, wa);
+          wa = fma(h01.y, x01.y, wa);
+          wa = fma(h23.x, x23.x, wa);
+          wa = fma(h23.y, x23.y, wa);
+          za = fma(s01.x, x01.x, za);
+          za = fma(s01.y, x01.y, za);
+          za = fma(s23.x, x23.x, za);
+          za = fma(s23.y, x23.y, za);
+        }
+        w[rr] = wa + wb;
+        z[rr] = za + zb;
       }
 
       // ---- first Gram-Schmidt pass dot products = projection column k
@@ -229,32 +260,38 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             if (i < NU) {
 #pragma unroll
               for (int rr = 0; rr < R; ++rr) {
-                ph = fma(q[rr][i], w[rr], ph);
-                ps = fma(q[rr][i], z[rr], ps);
+                ph = fma(qv[rr][i], w[rr], ph);
+                ps = fma(qv[rr][i], z[rr], ps);
               }
             }
             v[t] = ph;
             v[8 + t] = ps;
           }
-          const double r = wave_reduce_scatter<4>(v, lane);
-          if ((lane & 3) == 0) s_red[wave][c * 16 + (lane >> 2)] = r;
+          reduce16(v);
+          if ((lane & 15) == 0) {
+            const int base = c * 16 + ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) s_red[wave][base + t] = v[t];
+          }
         }
       }
       {
         double ww = 0.0;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-        ww = wave_sum(ww);
+        ww = wave_allreduce(ww);
         if (lane == 0) s_red[wave][16 * NCH] = ww;
       }
       __syncthreads();
       {
         const int nval = 16 * (kc + 1);
-        for (int t = tid; t < nval; t += KTPB)
-          s_fin[t] = ((s_red[0][t] + s_red[1][t]) + s_red[2][t]) + s_red[3][t];
-        if (tid == 0)
-          s_fin[16 * NCH] = ((s_red[0][16 * NCH] + s_red[1][16 * NCH]) + s_red[2][16 * NCH]) +
-                            s_red[3][16 * NCH];
+        for (int t = tid; t <= nval; t += KTPB) {
+          const int tt = (t == nval) ? 16 * NCH : t;
+          double acc = s_red[0][tt];
+#pragma unroll
+          for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
+          s_fin[tt] = acc;
+        }
       }
       __syncthreads();
       const double ww1 = s_fin[16 * NCH];
@@ -269,7 +306,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       }
       if (k == nu_max - 1) break;
 
-      // ---- w -= Q h[:, k]
+      // ---- w -= Q h[:, k], then the second pass c = Q^T w (one sweep)
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         if (c <= kc) {
@@ -279,12 +316,11 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             if (i < NU) {
               const double hi = s_fin[c * 16 + t];
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr) w[rr] = fma(-q[rr][i], hi, w[rr]);
+              for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], hi, w[rr]);
             }
           }
         }
       }
-      // ---- second pass: c = Q^T w
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         if (c <= kc) {
@@ -295,29 +331,35 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             double p = 0.0;
             if (i < NU) {
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr) p = fma(q[rr][i], w[rr], p);
+              for (int rr = 0; rr < R; ++rr) p = fma(qv[rr][i], w[rr], p);
             }
             v[t] = p;
           }
-          const double r = wave_reduce_scatter<3>(v, lane);
-          if ((lane & 7) == 0) s_red[wave][c * 8 + (lane >> 3)] = r;
+          reduce8(v);
+          if ((lane & 15) == 0) {
+            const int base = c * 8 + ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2;
+            s_red[wave][base] = v[0];
+            s_red[wave][base + 1] = v[1];
+          }
         }
       }
       {
         double ww = 0.0;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-        ww = wave_sum(ww);
+        ww = wave_allreduce(ww);
         if (lane == 0) s_red[wave][8 * NCH] = ww;
       }
       __syncthreads();
       {
         const int nval = 8 * (kc + 1);
-        for (int t = tid; t < nval; t += KTPB)
-          s_fin[t] = ((s_red[0][t] + s_red[1][t]) + s_red[2][t]) + s_red[3][t];
-        if (tid == 0)
-          s_fin[8 * NCH] = ((s_red[0][8 * NCH] + s_red[1][8 * NCH]) + s_red[2][8 * NCH]) +
-                           s_red[3][8 * NCH];
+        for (int t = tid; t <= nval; t += KTPB) {
+          const int tt = (t == nval) ? 8 * NCH : t;
+          double acc = s_red[0][tt];
+#pragma unroll
+          for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
+          s_fin[tt] = acc;
+        }
       }
       __syncthreads();
       double csq = 0.0;
@@ -331,7 +373,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
               const double ci = s_fin[c * 8 + t];
               csq = fma(ci, ci, csq);
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr) w[rr] = fma(-q[rr][i], ci, w[rr]);
+              for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], ci, w[rr]);
             }
           }
         }
@@ -343,10 +385,13 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         double ww = 0.0;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-        ww = wave_sum(ww);
+        ww = wave_allreduce(ww);
         if (lane == 0) s_red[wave][0] = ww;
         __syncthreads();
-        beta2 = ((s_red[0][0] + s_red[1][0]) + s_red[2][0]) + s_red[3][0];
+        double acc = s_red[0][0];
+#pragma unroll
+        for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][0];
+        beta2 = acc;
       }
       const double beta = sqrt(fmax(beta2, 0.0));
       if (!(beta > a.breakdown * sqrt(ww1))) {
@@ -356,13 +401,28 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       const double inv = 1.0 / beta;
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
-#pragma unroll
-      for (int i = 1; i < NU; ++i) {
-        if (i == k + 1) {
-#pragma unroll
-          for (int rr = 0; rr < R; ++rr) q[rr][i] = w[rr];
-        }
+      // q_{k+1} into its register column: k is uniform, so a switch on it is a
+      // scalar branch and costs no vector instructions per column slot
+      switch (k + 1) {
+#define MAG_QSTORE(I)                                        \
+  case I:                                                    \
+    if (I < NU) {                                            \
+      _Pragma("unroll") for (int rr = 0; rr < R; ++rr) qv[rr][I < NU ? I : 0] = w[rr]; \
+    }                                                        \
+    break;
+        MAG_QSTORE(1) MAG_QSTORE(2) MAG_QSTORE(3) MAG_QSTORE(4) MAG_QSTORE(5) MAG_QSTORE(6)
+        MAG_QSTORE(7) MAG_QSTORE(8) MAG_QSTORE(9) MAG_QSTORE(10) MAG_QSTORE(11) MAG_QSTORE(12)
+        MAG_QSTORE(13) MAG_QSTORE(14) MAG_QSTORE(15) MAG_QSTORE(16) MAG_QSTORE(17) MAG_QSTORE(18)
+        MAG_QSTORE(19) MAG_QSTORE(20) MAG_QSTORE(21) MAG_QSTORE(22) MAG_QSTORE(23) MAG_QSTORE(24)
+        MAG_QSTORE(25) MAG_QSTORE(26) MAG_QSTORE(27) MAG_QSTORE(28) MAG_QSTORE(29) MAG_QSTORE(30)
+        MAG_QSTORE(31) MAG_QSTORE(32) MAG_QSTORE(33) MAG_QSTORE(34) MAG_QSTORE(35) MAG_QSTORE(36)
+        MAG_QSTORE(37) MAG_QSTORE(38) MAG_QSTORE(39) MAG_QSTORE(40) MAG_QSTORE(41) MAG_QSTORE(42)
+        MAG_QSTORE(43) MAG_QSTORE(44) MAG_QSTORE(45) MAG_QSTORE(46) MAG_QSTORE(47)
+#undef MAG_QSTORE
+        default:
+          break;
       }
+      static_assert(NU <= 48, "basis store covers 48 columns");
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         const int r = tid + KTPB * rr;
@@ -383,20 +443,37 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         if (r == ell) {
           double* u = a.urow + slot * (int64_t)cap;
 #pragma unroll
-          for (int i = 0; i < NU; ++i) u[i] = q[rr][i];
+          for (int i = 0; i < NU; ++i) u[i] = qv[rr][i];
           for (int i = NU; i < cap; ++i) u[i] = 0.0;
         }
         const int p = a.full ? r : (int)s_pat[r];
         if (p >= 0) {
           double* dst = a.qpat + (slot * (int64_t)a.pat_stride + p) * cap;
 #pragma unroll
-          for (int i = 0; i < NU; ++i) dst[i] = q[rr][i];
+          for (int i = 0; i < NU; ++i) dst[i] = qv[rr][i];
           for (int i = NU; i < cap; ++i) dst[i] = 0.0;
         }
       }
     }
     __syncthreads();
   }
+}
+
+// Thread count and rows per thread: nu <= 30 fits one row per thread in 168
+// VGPRs (768 threads, three waves per SIMD, clusters up to 768 orbitals);
+// larger nu uses 512 threads with two rows each.
+template <int NU>
+struct KrylovShape {
+  static constexpr int TPB = NU <= 30 ? 768 : 512;
+  static constexpr int R = NU <= 30 ? 1 : 2;
+};
+
+template <int NU>
+static hipError_t launch_nu(const KrylovArgs& a, int grid, hipStream_t s) {
+  constexpr int T = KrylovShape<NU>::TPB;
+  constexpr int R = KrylovShape<NU>::R;
+  hipLaunchKernelGGL((krylov_kernel<NU, R, T>), dim3(grid), dim3(T), 0, s, a);
+  return hipGetLastError();
 }
 
 int krylov_capacity(int nu) {
@@ -406,34 +483,25 @@ int krylov_capacity(int nu) {
   return 0;
 }
 
-template <int NU, int R>
-static hipError_t launch_one(const KrylovArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((krylov_kernel<NU, R>), dim3(grid), dim3(KTPB), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int NU>
-static hipError_t launch_r(const KrylovArgs& a, int R, int grid, hipStream_t s) {
-  switch (R) {
-    case 1: return launch_one<NU, 1>(a, grid, s);
-    case 2: return launch_one<NU, 2>(a, grid, s);
-    case 3: return launch_one<NU, 3>(a, grid, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_krylov(const KrylovArgs& a, int cap, int rows_per_thread, int grid,
-                         hipStream_t s) {
+int krylov_rows(int cap) {  // cluster orbitals one workgroup can hold
   switch (cap) {
-    case 12: return launch_r<12>(a, rows_per_thread, grid, s);
-    case 20: return launch_r<20>(a, rows_per_thread, grid, s);
-    case 30: return launch_r<30>(a, rows_per_thread, grid, s);
-    case 40: return launch_r<40>(a, rows_per_thread, grid, s);
-    case 48: return launch_r<48>(a, rows_per_thread, grid, s);
-    default: return hipErrorInvalidValue;
+    case 12: return KrylovShape<12>::TPB * KrylovShape<12>::R;
+    case 20: return KrylovShape<20>::TPB * KrylovShape<20>::R;
+    case 30: return KrylovShape<30>::TPB * KrylovShape<30>::R;
+    case 40: return KrylovShape<40>::TPB * KrylovShape<40>::R;
+    default: return KrylovShape<48>::TPB * KrylovShape<48>::R;
   }
 }
 
-int krylov_threads() { return KTPB; }
+hipError_t launch_krylov(const KrylovArgs& a, int cap, int grid, hipStream_t s) {
+  switch (cap) {
+    case 12: return launch_nu<12>(a, grid, s);
+    case 20: return launch_nu<20>(a, grid, s);
+    case 30: return launch_nu<30>(a, grid, s);
+    case 40: return launch_nu<40>(a, grid, s);
+    case 48: return launch_nu<48>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 }  // namespace mag

@@ -82,7 +82,9 @@ struct KrylovArgs {
   const int32_t* clus_atoms;
   const int32_t* cols;     // columns of this launch, in slot order
   int64_t ncols;
-  int32_t* queue;          // persistent queue counter, or nullptr
+  int32_t* queue;          // persistent: one counter per queue, or nullptr (one column per WG)
+  const int64_t* qbeg;     // persistent: slot range [qbeg[q], qbeg[q+1]) of queue q
+  int nqueue;              // persistent: number of queues (workgroup w starts on queue w % nqueue)
   int nu;                  // requested Krylov dimension (<= template capacity)
   double breakdown;
   double* hs;              // per slot: h (NU x NU, column k rows i<=k) then s
@@ -135,10 +137,10 @@ struct DensityArgs {
 // --------------------------------------------------------------------------
 // launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
-hipError_t launch_krylov(const KrylovArgs& a, int cap, int rows_per_thread, int grid,
-                         hipStream_t s);
+hipError_t launch_krylov(const KrylovArgs& a, int cap, int grid, hipStream_t s);
+constexpr int KRYLOV_QUEUES = 8;  // one work queue per XCD
 int krylov_capacity(int nu);  // template capacity used for nu (0 if unsupported)
-int krylov_threads();
+int krylov_rows(int cap);  // largest cluster (orbitals) the kernel for cap holds
 hipError_t launch_eig(const EigArgs& a, hipStream_t s);
 hipError_t launch_density(const DensityArgs& a, hipStream_t s);
 
@@ -237,7 +239,8 @@ struct mag_ctx {
   std::vector<int32_t> h_clus_size;   // atoms per cluster
   std::vector<int32_t> h_bcount;      // blocks per block row
   std::vector<int64_t> h_rowptr;      // CSR row pointers (host copy)
-  std::vector<int32_t> h_order;       // columns, largest clusters first
+  std::vector<int32_t> h_order;       // columns in spatial (Morton) order of their atoms
+  std::vector<int64_t> h_qbeg;        // slot ranges of the per-XCD queues over h_order
   int64_t sum_cluster_nnz = 0;
 
   // solve state
@@ -246,7 +249,7 @@ struct mag_ctx {
   mag_opts opts{};
   int nu = 0;
   mag::DevBuf eps, w, nu_eff, state, partials, P, rho, pi;
-  mag::DevBuf k_hs, k_urow, k_qpat, k_nu, k_npat, k_cols, k_queue, errflag;
+  mag::DevBuf k_hs, k_urow, k_qpat, k_nu, k_npat, k_cols, k_queue, k_qbeg, errflag;
   mag::DevBuf tmp_cols, tmp_off, tmp_out;
   int64_t batch_cols = 0;
   mag::MuState h_state{};

@@ -4,20 +4,21 @@
 // N(mu) = sum_jk w_jk f((eps_jk - mu)/kT) over the valid Ritz pairs
 // (k < nu_eff[j]).  Plain bisection halves [lo, hi] at mid = lo + (hi - lo)/2
 // and keeps the upper half when N(mid) < N_e.  To cut the number of grid-wide
-// reductions, each launch evaluates N at all 63 midpoints of the next six
+// reductions, each launch evaluates N at all 31 midpoints of the next five
 // halvings (the binary tree of intervals below the current bracket, each node's
 // midpoint formed exactly as plain bisection would) and then walks the tree
 // with the plain rule; the result is the same sequence of brackets as plain
-// bisection, six levels per launch.  Reductions are deterministic: fixed
+// bisection, five levels per launch.  Reductions are deterministic: fixed
 // grid-stride partition, fixed in-block order, and the last block to finish
 // sums the per-block partials in block order.
 #include "mag_internal.h"
+#include "wave.h"
 
 namespace mag {
 
 constexpr int MTPB = 256;
-constexpr int MLEV = 6;
-constexpr int MPTS = (1 << MLEV) - 1;  // 63
+constexpr int MLEV = 5;
+constexpr int MPTS = (1 << MLEV) - 1;  // 31
 
 int mu_points_per_round() { return MPTS; }
 int mu_levels_per_round() { return MLEV; }
@@ -40,33 +41,6 @@ __device__ __forceinline__ double entropy_mu(double x) {
   return -(f * lnf + g * lng);
 }
 
-template <int LOG>
-__device__ __forceinline__ double reduce_scatter(double* v, int lane) {
-#pragma unroll
-  for (int step = 0; step < LOG; ++step) {
-    const int off = 32 >> step;
-    const bool up = (lane & off) != 0;
-    const int half = (1 << LOG) >> (step + 1);
-#pragma unroll
-    for (int t = 0; t < (1 << LOG) / 2; ++t) {
-      if (t < half) {
-        const double keep = up ? v[t + half] : v[t];
-        const double send = up ? v[t] : v[t + half];
-        v[t] = keep + __shfl_xor(send, off);
-      }
-    }
-  }
-  double x = v[0];
-#pragma unroll
-  for (int off = 32 >> LOG; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-__device__ __forceinline__ double wsum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
 __device__ __forceinline__ double wmin(double x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off));
@@ -153,9 +127,9 @@ __global__ __launch_bounds__(MTPB) void mu_init_kernel(const double* eps, const 
 __global__ __launch_bounds__(MTPB) void mu_round_kernel(const double* eps, const double* w,
                                                         const int32_t* nu_eff, int64_t M, int nu,
                                                         MuState* st, double* partials) {
-  __shared__ double s_pts[64];
-  __shared__ double s_red[MTPB / 64][64];
-  __shared__ double s_N[64];
+  __shared__ double s_pts[32];
+  __shared__ double s_red[MTPB / 64][32];
+  __shared__ double s_N[32];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (st->done) return;  // the same value in every block of this launch
   const double lo0 = st->lo, hi0 = st->hi, kT = st->kT;
@@ -174,9 +148,9 @@ __global__ __launch_bounds__(MTPB) void mu_round_kernel(const double* eps, const
     s_pts[tid] = 0.0;
   }
   __syncthreads();
-  double acc[64];
+  double acc[32];
 #pragma unroll
-  for (int p = 0; p < 64; ++p) acc[p] = 0.0;
+  for (int p = 0; p < 32; ++p) acc[p] = 0.0;
   const int64_t total = M * nu;
   for (int64_t idx = blockIdx.x * (int64_t)MTPB + tid; idx < total;
        idx += (int64_t)gridDim.x * MTPB) {
@@ -188,18 +162,22 @@ __global__ __launch_bounds__(MTPB) void mu_round_kernel(const double* eps, const
       for (int p = 0; p < MPTS; ++p) acc[p] = fma(ww, fermi_mu((e - s_pts[p]) / kT), acc[p]);
     }
   }
-  const double r = reduce_scatter<6>(acc, lane);  // lane p holds point p
-  s_red[wv][lane] = r;
+  reduce32(acc);  // acc[t] = total of point 16 b5 + 8 b4 + t
+  if ((lane & 15) == 0) {
+    const int base = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s_red[wv][base + t] = acc[t];
+  }
   __syncthreads();
-  if (tid < 64) {
+  if (tid < 32) {
     double t = s_red[0][tid];
     for (int q = 1; q < MTPB / 64; ++q) t += s_red[q][tid];
-    partials[64 * blockIdx.x + tid] = t;
+    partials[32 * blockIdx.x + tid] = t;
   }
   if (last_block(st)) {
-    if (tid < 64) {
+    if (tid < 32) {
       double t = 0.0;
-      for (unsigned q = 0; q < gridDim.x; ++q) t += partials[64 * q + tid];
+      for (unsigned q = 0; q < gridDim.x; ++q) t += partials[32 * q + tid];
       s_N[tid] = t;
     }
     __syncthreads();
@@ -254,8 +232,8 @@ __global__ __launch_bounds__(MTPB) void energy_kernel(const double* eps, const d
       v[2] = fma(ww, f, v[2]);
     }
   }
-  const double r = reduce_scatter<2>(v, lane);  // lane l holds value l >> 4
-  if ((lane & 15) == 0) s_red[wv][lane >> 4] = r;
+  reduce4(v);  // v[0] = total of value 2 b5 + b4
+  if ((lane & 15) == 0) s_red[wv][((lane >> 5) & 1) * 2 + ((lane >> 4) & 1)] = v[0];
   __syncthreads();
   if (tid < 4) {
     double t = s_red[0][tid];

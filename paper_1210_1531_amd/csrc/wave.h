@@ -1,0 +1,102 @@
+// Deterministic wave-level reductions of FP64 values on gfx950.
+//
+// The two cross-row levels use v_permlane32_swap / v_permlane16_swap, which
+// exchange halves of two registers between lane groups, so a reduce-scatter
+// step needs no per-lane selects; the four levels inside a row of 16 lanes use
+// DPP moves (row_mirror, row_half_mirror, quad xor 2, quad xor 1), which pair
+// lanes i with 15-i, then mirror within 8, then i^2, then i^1 -- a valid
+// butterfly over the 16 lanes.  The summation order is fixed, so results are
+// bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mag {
+
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 16 lanes of each row; every lane of the row gets the total
+__device__ __forceinline__ double row_allreduce(double x) {
+  x += dpp_f64<DPP_ROW_MIRROR>(x);
+  x += dpp_f64<DPP_ROW_HALF_MIRROR>(x);
+  x += dpp_f64<DPP_QUAD_XOR2>(x);
+  x += dpp_f64<DPP_QUAD_XOR1>(x);
+  return x;
+}
+
+// a in lanes 0-31 keeps a, lanes 32-63 receive b of the partner half:
+// returns a(l) + a(l^32) in lanes 0-31 and b(l^32) + b(l) in lanes 32-63
+__device__ __forceinline__ double swap32_add(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// rows 0 and 2 (lane bit 4 clear) get a(l) + a(l^16), rows 1 and 3 get b(l^16) + b(l)
+__device__ __forceinline__ double swap16_add(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// total over all 64 lanes, in every lane
+__device__ __forceinline__ double wave_allreduce(double x) {
+  x = swap32_add(x, x);
+  x = swap16_add(x, x);
+  return row_allreduce(x);
+}
+
+// 16 values per lane -> afterwards v[t], t < 4, holds the wave total of value
+// 8 * b5 + 4 * b4 + t, where b5, b4 are bits 5 and 4 of the lane id
+__device__ __forceinline__ void reduce16(double* v) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = swap32_add(v[t], v[t + 8]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = swap16_add(v[t], v[t + 4]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = row_allreduce(v[t]);
+}
+
+// 8 values per lane -> v[t], t < 2, holds the total of value 4 * b5 + 2 * b4 + t
+__device__ __forceinline__ void reduce8(double* v) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = swap32_add(v[t], v[t + 4]);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) v[t] = swap16_add(v[t], v[t + 2]);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) v[t] = row_allreduce(v[t]);
+}
+
+// 32 values per lane -> v[t], t < 8, holds the total of value 16 * b5 + 8 * b4 + t
+__device__ __forceinline__ void reduce32(double* v) {
+#pragma unroll
+  for (int t = 0; t < 16; ++t) v[t] = swap32_add(v[t], v[t + 16]);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = swap16_add(v[t], v[t + 8]);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = row_allreduce(v[t]);
+}
+
+// 4 values per lane -> v[0] holds the total of value 2 * b5 + b4
+__device__ __forceinline__ void reduce4(double* v) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) v[t] = swap32_add(v[t], v[t + 2]);
+  v[0] = swap16_add(v[0], v[1]);
+  v[0] = row_allreduce(v[0]);
+}
+
+}  // namespace mag

@@ -25,7 +25,8 @@ class MagError(RuntimeError):
         self.status = status
 
 
-_WORKFLOWS = {"recompute": L.MAG_WORKFLOW_RECOMPUTE, "store": L.MAG_WORKFLOW_STORE}
+_WORKFLOWS = {"recompute": L.MAG_WORKFLOW_RECOMPUTE, "store": L.MAG_WORKFLOW_STORE,
+              "auto": L.MAG_WORKFLOW_AUTO}
 _SCHEDULES = {"auto": L.MAG_SCHED_AUTO, "persistent": L.MAG_SCHED_PERSISTENT,
               "grid": L.MAG_SCHED_GRID, "plain": L.MAG_SCHED_PLAIN}
 
@@ -38,7 +39,7 @@ def _is_dev(x):
 
 
 def make_opts(nu=30, kT=0.1, n_electrons=0.0, mu_tol=1e-12, mu_fixed=None, breakdown=1e-12,
-              workflow="recompute", schedule="auto") -> L.MagOpts:
+              workflow="auto", schedule="auto") -> L.MagOpts:
     o = L.MagOpts()
     L.load().mag_opts_default(C.byref(o))
     o.nu = int(nu)

@@ -84,7 +84,7 @@ def test_host_only_entry_points():
     assert lib.mag_last_error(None) == b"context is NULL"
     o = make_opts(nu=20, kT=0.2, n_electrons=8.0)
     assert o.nu == 20 and o.kT == 0.2 and o.mu_fixed != o.mu_fixed  # NaN
-    assert o.workflow == L.MAG_WORKFLOW_RECOMPUTE and o.schedule == L.MAG_SCHED_AUTO
+    assert o.workflow == L.MAG_WORKFLOW_AUTO and o.schedule == L.MAG_SCHED_AUTO
     assert lib.mag_create(None, 0, None) == L.MAG_EINVAL
 
 
