@@ -59,7 +59,8 @@ enum mag_status {
   MAG_EBRACKET = -5,    /* n_electrons outside (0, 2M) or no sign change in the bracket */
   MAG_ESTATE = -6,      /* call out of order (e.g. density before solve) */
   MAG_ENONFINITE = -7,  /* NaN or Inf in the input or in an intermediate result */
-  MAG_EUNSUPPORTED = -8 /* size beyond a documented limit */
+  MAG_EUNSUPPORTED = -8, /* size beyond a documented limit */
+  MAG_ENOCONV = -9       /* the projected eigensolver did not converge */
 };
 
 enum mag_mem { MAG_HOST = 0, MAG_DEVICE = 1 };
@@ -218,7 +219,7 @@ void mag_opts_default(mag_opts* opts);
  * bisection (mid = lo + (hi - lo)/2 on [min eps - 40 kT, max eps + 40 kT]).
  * E_band = sum w f eps, A_free = E_band - kT sum w s(f).  Any output pointer
  * may be NULL.  Errors: MAG_ESTATE (no system), MAG_EINVAL (opts),
- * MAG_EBRACKET, MAG_ENOTPD, MAG_ENONFINITE. */
+ * MAG_EBRACKET, MAG_ENOTPD, MAG_ENONFINITE, MAG_ENOCONV. */
 int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu,
                       double* E_band, double* A_free);
 

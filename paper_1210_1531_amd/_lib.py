@@ -15,9 +15,11 @@ MAG_EBRACKET = -5
 MAG_ESTATE = -6
 MAG_ENONFINITE = -7
 MAG_EUNSUPPORTED = -8
+MAG_ENOCONV = -9
 STATUS_NAMES = {
     0: "MAG_OK", -1: "MAG_EINVAL", -2: "MAG_ENOMEM", -3: "MAG_EHIP", -4: "MAG_ENOTPD",
     -5: "MAG_EBRACKET", -6: "MAG_ESTATE", -7: "MAG_ENONFINITE", -8: "MAG_EUNSUPPORTED",
+    -9: "MAG_ENOCONV",
 }
 
 MAG_HOST = 0

@@ -87,6 +87,8 @@ int take_errors(mag_ctx* ctx, const char* where) {
     return fail(ctx, MAG_EINVAL, w + ": a block-row atom lies outside the column's cluster");
   if (flags & KERR_CAPACITY)
     return fail(ctx, MAG_EUNSUPPORTED, w + ": a cluster or block row exceeds the library limits");
+  if (flags & KERR_NOCONV)
+    return fail(ctx, MAG_ENOCONV, w + ": the projected eigensolver did not converge");
   return fail(ctx, MAG_EHIP, w + ": kernel error flag " + std::to_string(flags));
 }
 
@@ -213,8 +215,11 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
   if (n == 0) return MAG_OK;
   const int cap = krylov_capacity(job.nu);
   const int pat_stride = job.full ? NC_MAX : PAT_MAX;
+  const int rec_cap = eig_rec_cap(cap), sweep_cap = eig_sweep_cap(cap);
   const size_t per_slot =
       sizeof(double) * ((size_t)2 * cap * cap + cap + (size_t)pat_stride * cap) + 2 * sizeof(int32_t) +
+      sizeof(double) * ((size_t)5 * cap + 2 * (size_t)rec_cap) +
+      sizeof(int32_t) * ((size_t)sweep_cap + 2) +
       (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0);
   const char* env = std::getenv("MAG_SCRATCH_GB");
   const double budget_gb = env ? std::atof(env) : 8.0;
@@ -228,6 +233,13 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
   ALLOC(ctx->k_npat, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_queue, sizeof(int32_t) * KRYLOV_QUEUES);
   ALLOC(ctx->k_qbeg, sizeof(int64_t) * (KRYLOV_QUEUES + 1));
+  ALLOC(ctx->k_trid, sizeof(double) * bsz * 4 * cap);
+  ALLOC(ctx->k_evu, sizeof(double) * bsz * cap);
+  ALLOC(ctx->k_rot, sizeof(double) * bsz * 2 * (size_t)rec_cap);
+  ALLOC(ctx->k_sweep, sizeof(int32_t) * bsz * (size_t)sweep_cap);
+  ALLOC(ctx->k_qlst, sizeof(int32_t) * bsz);
+  ALLOC(ctx->k_fbl, sizeof(int32_t) * bsz);
+  ALLOC(ctx->k_fbc, sizeof(int32_t));
   double* Pbuf = job.P_store;
   if (job.want_P && !job.P_store) {
     ALLOC(ctx->tmp_out, sizeof(double) * bsz * (size_t)pat_stride * job.nu);
@@ -287,6 +299,15 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
     ea.pat_stride = pat_stride;
     ea.out_by_slot = job.out_by_slot;
     ea.err = ka.err;
+    ea.trid = ctx->k_trid.as<double>();
+    ea.evu = ctx->k_evu.as<double>();
+    ea.rot = ctx->k_rot.as<double>();
+    ea.sweep = ctx->k_sweep.as<int32_t>();
+    ea.qlst = ctx->k_qlst.as<int32_t>();
+    ea.fb_list = ctx->k_fbl.as<int32_t>();
+    ea.fb_count = ctx->k_fbc.as<int32_t>();
+    ea.rec_cap = rec_cap;
+    ea.sweep_cap = sweep_cap;
 
     if (schedule == MAG_SCHED_PLAIN) {
       for (int64_t q = 0; q < cnt; ++q) {
@@ -1242,7 +1263,8 @@ int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
                           &ctx->partials, &ctx->P, &ctx->rho, &ctx->pi, &ctx->k_hs,
                           &ctx->k_urow, &ctx->k_qpat, &ctx->k_nu, &ctx->k_npat, &ctx->k_cols,
                           &ctx->k_queue, &ctx->errflag, &ctx->tmp_cols, &ctx->tmp_off,
-                          &ctx->tmp_out};
+                          &ctx->tmp_out, &ctx->k_trid, &ctx->k_evu, &ctx->k_rot,
+                          &ctx->k_sweep, &ctx->k_qlst, &ctx->k_fbl, &ctx->k_fbc};
   for (const DevBuf* b : bufs) bytes += (int64_t)b->bytes;
   ctx->stats.device_bytes = bytes;
   *out = ctx->stats;

@@ -1,110 +1,78 @@
-// Projected eigensolve and spectral data of each column (batched, one wave
-// per column).
+// Projected eigensolve and spectral data of each column.
 //
 // Input per column: the projected pencil (h, s) = (Q^T H_C Q, Q^T S_C Q) of
 // size n = nu_eff (upper triangles, column k rows i <= k), the row u = Q^T e_l
-// and the pattern rows of Q.  Steps:
-//   s = L L^T (Cholesky), C = L^-1 h L^-T, C = V diag(eps) V^T by the cyclic
-//   Jacobi method (round-robin parallel ordering, n/2 rotations per round),
-//   c = L^-T V (so h c = eps s c and c^T s c = I), eigenpairs sorted
-//   ascending;
-//   d = c^T u = (Qc)^T e_l,  g = c^T s e_1 = (Qc)^T S_C e_l  (q_1 = e_l),
-//   weights w_k = 2 d_k g_k (spin factor 2);
-//   optionally P_pk = (Q_pat c)_pk d_k on the pattern rows, from which pass 2
-//   forms rho = 2 P f and pi = 2 P (f eps) (Eq. 2 on the Ritz spectrum).
+// and the pattern rows of Q.  The generalized problem h c = eps s c is solved
+// in three batched kernels:
+//
+//  1. reduction (one wave per column): s = L L^T (Cholesky),
+//     C = L^-1 h L^-T, and the Householder tridiagonalization
+//     C = Q_H T Q_H^T, Q_H = P_0 P_1 ... P_{n-3}, P_k = I - beta_k v_k v_k^T
+//     (Golub & Van Loan's house vectors, v_k[k+1] = 1).  L overwrites the h
+//     block of the column's scratch, the dense reflector rows v_k the s block.
+//  2. QL (one lane per column): the implicit QL method with Wilkinson-type
+//     shifts on T (diagonal d, subdiagonal e) gives the eigenvalues.  The
+//     plane rotations of every sweep are recorded instead of applied, so each
+//     lane carries only d and e.
+//  3. vectors (one wave per column): Z_T is rebuilt by replaying the recorded
+//     rotations on Z = I (lane i holds row i of Z; every register index is a
+//     compile-time constant), then c = L^-T Q_H Z_T column by column (lane k
+//     holds eigenvector k), so h c = eps s c and c^T s c = I.  Then
+//       d = c^T u = (Qc)^T e_l,  g = c^T s e_1 = (Qc)^T S_C e_l  (q_1 = e_l),
+//       w_k = 2 d_k g_k (spin factor 2), eigenpairs ranked ascending,
+//     and optionally P_pk = (Q_pat c)_pk d_k on the pattern rows, from which
+//     pass 2 forms rho = 2 P f and pi = 2 P (f eps) (Eq. 2 on the Ritz
+//     spectrum).
+//  A column whose rotation record would overflow its fixed slots (or whose
+//  QL did not converge in the lane kernel) is finished by a fallback kernel
+//  that runs the same QL inside one wave with the rotations applied directly.
 #include "mag_internal.h"
+#include "wave.h"
 
 namespace mag {
 
 constexpr int ETPB = 64;
-constexpr int MAXP = NU_MAX / 2;  // rotations per round at most
+constexpr int QL_MAXIT = 60;  // QL iterations per eigenvalue before giving up
 
-__device__ __forceinline__ double wave_sum64(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
+int eig_rec_cap(int cap) { return 2 * cap * cap; }
+int eig_sweep_cap(int cap) { return 4 * cap; }
 
-__device__ __forceinline__ void round_robin(int m, int r, int p, int& i, int& j) {
-  // circle method: player m-1 fixed, players 0..m-2 rotate with the round
-  if (p == 0) {
-    i = m - 1;
-    j = r;
-  } else {
-    const int mm = m - 1;  // r, p < mm, so one conditional subtraction wraps
-    i = r + p;
-    i -= (i >= mm) ? mm : 0;
-    j = r - p + mm;
-    j -= (j >= mm) ? mm : 0;
-  }
-  if (i > j) {
-    const int t = i;
-    i = j;
-    j = t;
-  }
-}
-
-__global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
+// ---------------------------------------------------------------------------
+// 1. Cholesky, C = L^-1 h L^-T, Householder tridiagonalization
+template <int NM>
+__global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
   extern __shared__ double sm[];
   const int64_t slot = blockIdx.x;
   if (slot >= a.ncols) return;
   const int lane = threadIdx.x;
-  const int cap = a.cap;
   const int n = a.nu_eff_in[slot];
-  const int j = a.cols[slot];
-  const int nuo = a.nu;
-  const int64_t oi = a.out_by_slot ? slot : (int64_t)j;  // output row
-
-  if (n <= 0) {
-    for (int k = lane; k < nuo; k += ETPB) {
-      a.eps[oi * nuo + k] = 0.0;
-      a.w[oi * nuo + k] = 0.0;
-    }
-    if (lane == 0) a.nu_eff_out[oi] = 0;
+  if (n <= 0 || n > NM) {
+    if (n > NM && lane == 0) atomicOr(a.err, (int)KERR_CAPACITY);
     return;
   }
-  const int m = n + (n & 1);  // even size; an odd n gets one decoupled dummy index
-  const int ld = m + 1;
-  const int half = m / 2;
-  double* A = sm;                 // m x ld
-  double* V = A + m * ld;         // m x ld
-  double* L = V + m * ld;         // m x ld
-  double2* rot = reinterpret_cast<double2*>(L + m * ld);  // (c, s) per pair, MAXP
-  double* ev = reinterpret_cast<double*>(rot + MAXP);      // eigenvalues (64)
-  double* dv = ev + 64;           // d (64)
-  double* gv = dv + 64;           // g (64)
-  double* uu = gv + 64;           // row l of Q (64)
-  double* s0 = uu + 64;           // first row of s (64)
-  int2* pij = reinterpret_cast<int2*>(s0 + 64);  // (i, j) per pair, MAXP
-  int* perm = reinterpret_cast<int*>(pij + MAXP); // perm[rank] = eigen index (64)
-  int* flag = perm + 64;
-  int2* btab = reinterpret_cast<int2*>(flag + 4);  // (p, q) of each 2x2 block
+  const int ld = n + 1;
+  double* A = sm;               // n x ld: h, then C
+  double* L = A + n * ld;       // n x ld: Cholesky factor below, reflectors above
+  double* vv = L + n * ld;      // Householder vector
+  double* ww = vv + NM;         // Householder update vector
+  double* li = ww + NM;         // 1 / L_ii
+  int* flag = reinterpret_cast<int*>(li + NM);
+  double* h = a.hs + slot * (int64_t)(2 * NM * NM);
+  double* s = h + NM * NM;
+  double* tr = a.trid + slot * (int64_t)(4 * NM);
 
-  const double* h = a.hs + slot * (int64_t)(2 * cap * cap);
-  const double* s = h + cap * cap;
-
-  for (int idx = lane; idx < m * m; idx += ETPB) {
-    const int i = idx / m, k = idx - (idx / m) * m;
-    double hv = 0.0, sv = 0.0;
-    if (i < n && k < n) {
-      const int lo = min(i, k), hi = max(i, k);
-      hv = h[(int64_t)hi * cap + lo];
-      sv = s[(int64_t)hi * cap + lo];
-    } else if (i == k) {
-      sv = 1.0;  // dummy index: identity overlap, zero h
-    }
-    A[i * ld + k] = hv;
-    L[i * ld + k] = sv;
+  for (int idx = lane; idx < n * n; idx += ETPB) {
+    const int i = idx / n, k = idx - (idx / n) * n;
+    const int lo = min(i, k), hi = max(i, k);
+    A[i * ld + k] = h[hi * NM + lo];
+    L[i * ld + k] = s[hi * NM + lo];
   }
-  if (lane < 64) {
-    uu[lane] = (lane < n) ? a.urow[slot * (int64_t)cap + lane] : 0.0;
-    s0[lane] = (lane < n) ? s[(int64_t)lane * cap + 0] : 0.0;  // s_{0 i} = s_{i 0}
-  }
+  if (lane < n) tr[3 * NM + lane] = s[lane * NM];  // s e_1 (s_{i0} = s_{0i})
   if (lane == 0) flag[0] = 0;
   __syncthreads();
 
-  // ---- Cholesky s = L L^T (lower triangle of L, in place)
-  for (int c = 0; c < m; ++c) {
+  // ---- Cholesky s = L L^T (lower triangle of L)
+  for (int c = 0; c < n; ++c) {
     if (lane == 0) {
       double d = L[c * ld + c];
       for (int p = 0; p < c; ++p) d -= L[c * ld + p] * L[c * ld + p];
@@ -112,207 +80,490 @@ __global__ __launch_bounds__(ETPB) void eig_kernel(EigArgs a) {
         flag[0] = 1;
         d = 1.0;
       }
-      L[c * ld + c] = sqrt(d);
+      const double r = sqrt(d);
+      L[c * ld + c] = r;
+      li[c] = 1.0 / r;
     }
     __syncthreads();
-    for (int i = c + 1 + lane; i < m; i += ETPB) {
-      double x = L[i * ld + c];
-      for (int p = 0; p < c; ++p) x -= L[i * ld + p] * L[c * ld + p];
-      L[i * ld + c] = x / L[c * ld + c];
+    if (lane > c && lane < n) {
+      double x = L[lane * ld + c];
+      for (int p = 0; p < c; ++p) x -= L[lane * ld + p] * L[c * ld + p];
+      L[lane * ld + c] = x * li[c];
     }
     __syncthreads();
   }
-  if (flag[0]) {
-    if (lane == 0) atomicOr(a.err, (int)KERR_NOTPD);
-  }
+  if (flag[0] && lane == 0) atomicOr(a.err, (int)KERR_NOTPD);
 
-  // ---- X = L^-1 h (into V), then C = L^-1 X^T (into A)
-  for (int col = lane; col < m; col += ETPB) {
-    for (int i = 0; i < m; ++i) {
-      double x = A[i * ld + col];
-      for (int p = 0; p < i; ++p) x -= L[i * ld + p] * V[p * ld + col];
-      V[i * ld + col] = x / L[i * ld + i];
+  // ---- X = L^-1 h, column `lane` in place; then C = X L^-T, row `lane` in place
+  if (lane < n) {
+    for (int i = 0; i < n; ++i) {
+      double x = A[i * ld + lane];
+      for (int p = 0; p < i; ++p) x -= L[i * ld + p] * A[p * ld + lane];
+      A[i * ld + lane] = x * li[i];
     }
   }
   __syncthreads();
-  for (int col = lane; col < m; col += ETPB) {
-    for (int i = 0; i < m; ++i) {
-      double x = V[col * ld + i];
-      for (int p = 0; p < i; ++p) x -= L[i * ld + p] * A[p * ld + col];
-      A[i * ld + col] = x / L[i * ld + i];
+  if (lane < n) {
+    double* row = A + lane * ld;
+    for (int i = 0; i < n; ++i) {
+      double x = row[i];
+      for (int p = 0; p < i; ++p) x -= L[i * ld + p] * row[p];
+      row[i] = x * li[i];
     }
   }
   __syncthreads();
-  for (int idx = lane; idx < m * m; idx += ETPB) {
-    const int i = idx / m, k = idx - (idx / m) * m;
+  for (int idx = lane; idx < n * n; idx += ETPB) {
+    const int i = idx / n, k = idx - (idx / n) * n;
     if (i < k) {
       const double v = 0.5 * (A[i * ld + k] + A[k * ld + i]);
       A[i * ld + k] = v;
       A[k * ld + i] = v;
     }
-    V[i * ld + k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
 
-  // ---- cyclic Jacobi with round-robin pairs; each round applies A <- J^T A J
-  // by 2x2 blocks: block (p, q) of rows {i_p, j_p} and columns {i_q, j_q}
-  // becomes R_p^T B R_q, so every block is read and written by one lane.
-  const int nblk = half * (half + 1) / 2;  // blocks with p <= q
-  for (int b = lane; b < nblk; b += ETPB) {  // static block table (p, q)
-    int p = 0, rem = b;
-    while (rem >= half - p) {
-      rem -= half - p;
-      ++p;
+  // ---- Householder: step k reflects rows and columns k+1..n-1 so that column
+  // k vanishes below the subdiagonal.  Lane i owns column i of the trailing
+  // block (C stays symmetric, so C v is taken column-wise).
+  for (int k = 0; k + 2 < n; ++k) {
+    const double x0 = A[k * ld + k + 1];
+    const double xi = (lane > k + 1 && lane < n) ? A[k * ld + lane] : 0.0;
+    const double sig = wave_allreduce(xi * xi);
+    double beta = 0.0, v0 = 1.0, sub = x0;
+    if (sig > 0.0) {
+      const double mu = sqrt(x0 * x0 + sig);
+      v0 = (x0 <= 0.0) ? x0 - mu : -sig / (x0 + mu);
+      beta = 2.0 * v0 * v0 / (sig + v0 * v0);
+      sub = mu;
     }
-    btab[b] = make_int2(p, p + rem);
-  }
-  // V rows: lane l updates row (l mod rows_span) for pairs p = l / rows_span + k * groups
-  const int span = m <= 32 ? 32 : 64;
-  const int vrow = lane & (span - 1);
-  const int vgrp = lane / span;          // 0 or 1
-  const int groups = ETPB / span;        // 2 or 1
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    if (lane < m) {
-      for (int i = 0; i < m; ++i) {
-        const double v = A[i * ld + lane];
-        tot += v * v;
-        off += (i != lane) ? v * v : 0.0;
-      }
+    const double vi = (lane == k + 1) ? 1.0 : xi / v0;  // zero outside k+1..n-1
+    if (lane < NM) vv[lane] = (lane > k && lane < n) ? vi : 0.0;
+    if (lane > k + 1 && lane < n) L[k * ld + lane] = vi;  // strictly upper part of L
+    if (lane == 0) {
+      tr[k] = A[k * ld + k];
+      tr[NM + k] = sub;
+      tr[2 * NM + k] = beta;
     }
-    off = wave_sum64(off);
-    tot = wave_sum64(tot);
-    if (!(off > 1e-30 * tot)) break;
-    for (int r = 0; r < m - 1; ++r) {
-      if (lane < half) {
-        int i, jj;
-        round_robin(m, r, lane, i, jj);
-        const double aij = A[i * ld + jj];
-        double c = 1.0, sn = 0.0;
-        if (aij != 0.0) {
-          const double tau = (A[jj * ld + jj] - A[i * ld + i]) / (2.0 * aij);
-          double t;
-          if (fabs(tau) > 1e150) t = 0.5 / tau;
-          else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = t * c;
-        }
-        rot[lane] = make_double2(c, sn);
-        pij[lane] = make_int2(i, jj);
+    __syncthreads();
+    if (beta != 0.0) {
+      // p = beta C v, w = p - (beta p^T v / 2) v
+      double p = 0.0;
+      if (lane > k && lane < n) {
+        for (int i = k + 1; i < n; ++i) p = fma(A[i * ld + lane], vv[i], p);
+        p *= beta;
       }
+      const double kk = 0.5 * beta * wave_allreduce((lane > k && lane < n) ? p * vv[lane] : 0.0);
+      const double wi = p - kk * ((lane > k && lane < n) ? vv[lane] : 0.0);
+      if (lane < NM) ww[lane] = (lane > k && lane < n) ? wi : 0.0;
       __syncthreads();
-      for (int b = lane; b < nblk; b += ETPB) {
-        const int2 pq = btab[b];
-        const int2 P = pij[pq.x], Q = pij[pq.y];
-        const double2 rp = rot[pq.x], rq = rot[pq.y];
-        const double x00 = A[P.x * ld + Q.x], x01 = A[P.x * ld + Q.y];
-        const double x10 = A[P.y * ld + Q.x], x11 = A[P.y * ld + Q.y];
-        // rows: new row i = c row_i - s row_j, new row j = s row_i + c row_j
-        const double y00 = rp.x * x00 - rp.y * x10, y01 = rp.x * x01 - rp.y * x11;
-        const double y10 = rp.y * x00 + rp.x * x10, y11 = rp.y * x01 + rp.x * x11;
-        // columns: new col i = c col_i - s col_j, new col j = s col_i + c col_j
-        const double z00 = rq.x * y00 - rq.y * y01, z01 = rq.y * y00 + rq.x * y01;
-        const double z10 = rq.x * y10 - rq.y * y11, z11 = rq.y * y10 + rq.x * y11;
-        A[P.x * ld + Q.x] = z00;
-        A[P.x * ld + Q.y] = z01;
-        A[P.y * ld + Q.x] = z10;
-        A[P.y * ld + Q.y] = z11;
-        if (pq.x != pq.y) {
-          A[Q.x * ld + P.x] = z00;
-          A[Q.y * ld + P.x] = z01;
-          A[Q.x * ld + P.y] = z10;
-          A[Q.y * ld + P.y] = z11;
-        }
-      }
-      // V <- V J
-      if (vrow < m) {
-        double* vr = V + vrow * ld;
-        for (int p = vgrp; p < half; p += groups) {
-          const int2 P = pij[p];
-          const double2 rp = rot[p];
-          const double x = vr[P.x], y = vr[P.y];
-          vr[P.x] = rp.x * x - rp.y * y;
-          vr[P.y] = rp.y * x + rp.x * y;
-        }
+      if (lane > k && lane < n) {
+        const double vl = vv[lane];
+        for (int i = k + 1; i < n; ++i) A[i * ld + lane] -= vv[i] * wi + ww[i] * vl;
       }
       __syncthreads();
     }
   }
-
-  // ---- eigenvalues, ascending order (ties by index), c = L^-T V
-  for (int k = lane; k < m; k += ETPB) ev[k] = A[k * ld + k];
+  if (lane == 0) {
+    if (n >= 2) {
+      tr[n - 2] = A[(n - 2) * ld + n - 2];
+      tr[NM + n - 2] = A[(n - 2) * ld + n - 1];
+      tr[2 * NM + n - 2] = 0.0;
+    }
+    tr[n - 1] = A[(n - 1) * ld + n - 1];
+    tr[NM + n - 1] = 0.0;
+    tr[2 * NM + n - 1] = 0.0;
+  }
   __syncthreads();
-  for (int k = lane; k < n; k += ETPB) {
-    int rank = 0;
-    const double e = ev[k];
+  // L (zero above the diagonal) over h; dense reflector rows over s
+  for (int idx = lane; idx < n * n; idx += ETPB) {
+    const int i = idx / n, k = idx - (idx / n) * n;
+    h[i * NM + k] = (k <= i) ? L[i * ld + k] : 0.0;
+    double v = 0.0;
+    if (i + 2 < n) v = (k == i + 1) ? 1.0 : ((k > i + 1) ? L[i * ld + k] : 0.0);
+    s[i * NM + k] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. QL on the tridiagonal, one lane per column, rotations recorded per sweep
+template <int NM>
+__global__ __launch_bounds__(ETPB) void ql_kernel(EigArgs a) {
+  const int64_t slot = (int64_t)blockIdx.x * ETPB + threadIdx.x;
+  if (slot >= a.ncols) return;  // no barriers below
+  const int n = a.nu_eff_in[slot];
+  if (n <= 0 || n > NM) {
+    a.qlst[slot] = 0;
+    return;
+  }
+  const double* tr = a.trid + slot * (int64_t)(4 * NM);
+  double d[NM], e[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    d[t] = (t < n) ? tr[t] : 0.0;
+    e[t] = (t < n) ? tr[NM + t] : 0.0;
+  }
+  double2* rec = reinterpret_cast<double2*>(a.rot) + slot * (int64_t)a.rec_cap;
+  int32_t* sw = a.sweep + slot * (int64_t)a.sweep_cap;
+  int nrec = 0, nsw = 0, status = 0;
+  for (int l = 0; l < n && status == 0; ++l) {
+    for (int iter = 0;; ++iter) {
+      int ms = n - 1;
+#pragma unroll
+      for (int t = NM - 2; t >= 0; --t) {
+        if (t >= l && t < n - 1) {
+          if (fabs(e[t]) <= 0x1p-52 * (fabs(d[t]) + fabs(d[t + 1]))) ms = t;
+        }
+      }
+      if (ms == l) break;
+      if (iter >= QL_MAXIT) {
+        status = -2;
+        break;
+      }
+      if (nsw >= a.sweep_cap || nrec + (ms - l) > a.rec_cap) {
+        status = -1;
+        break;
+      }
+      double dl = 0.0, dl1 = 0.0, el = 0.0, dm = 0.0;
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        if (t == l) {
+          dl = d[t];
+          el = e[t];
+        }
+        if (t == l + 1) dl1 = d[t];
+        if (t == ms) dm = d[t];
+      }
+      double g = (dl1 - dl) / (2.0 * el);
+      double r = sqrt(fma(g, g, 1.0));
+      g = dm - dl + el / (g + copysign(r, g));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      bool under = false;
+      int cnt = 0;
+#pragma unroll
+      for (int i = NM - 2; i >= 0; --i) {
+        if (i >= ms) continue;
+        if (i < l || under) break;
+        const double f = sn * e[i], b = cs * e[i];
+        // r = |(f, g)|; r == 0 only by underflow, and then the identity rotation
+        // (sn, cs) = (0, 1) gives d[i+1] -= p, and the sweep ends
+        const double q = fma(f, f, g * g);
+        const bool bad = !(q > 0.0);
+        const double rinv = bad ? 0.0 : rsqrt(q);
+        r = q * rinv;
+        e[i + 1] = r;
+        sn = f * rinv;
+        cs = bad ? 1.0 : g * rinv;
+        g = d[i + 1] - p;
+        r = fma(d[i] - g, sn, 2.0 * cs * b);
+        p = sn * r;
+        d[i + 1] = g + p;
+        g = fma(cs, r, -b);
+        rec[nrec + cnt] = make_double2(sn, cs);
+        ++cnt;
+        under = bad;
+      }
+      sw[nsw++] = (ms << 8) | cnt;
+      nrec += cnt;
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        if (!under && t == l) {
+          d[t] -= p;
+          e[t] = g;
+        }
+        if (t == ms) e[t] = 0.0;
+      }
+    }
+  }
+  double* ev = a.evu + slot * (int64_t)NM;
+#pragma unroll
+  for (int t = 0; t < NM; ++t)
+    if (t < n) ev[t] = d[t];
+  a.qlst[slot] = (status == 0) ? nsw : status;
+  if (status != 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)slot;
+}
+
+// the same QL inside one wave, rotations applied to the row of Z held by each lane
+template <int NM>
+__device__ __forceinline__ bool ql_wave(const double* tr, int n, double* z, double* ev, int lane) {
+  double d[NM], e[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    d[t] = (t < n) ? tr[t] : 0.0;
+    e[t] = (t < n) ? tr[NM + t] : 0.0;
+  }
+  bool ok = true;
+  for (int l = 0; l < n && ok; ++l) {
+    for (int iter = 0;; ++iter) {
+      int ms = n - 1;
+#pragma unroll
+      for (int t = NM - 2; t >= 0; --t) {
+        if (t >= l && t < n - 1) {
+          if (fabs(e[t]) <= 0x1p-52 * (fabs(d[t]) + fabs(d[t + 1]))) ms = t;
+        }
+      }
+      ms = __builtin_amdgcn_readfirstlane(ms);
+      if (ms == l) break;
+      if (iter >= QL_MAXIT) {
+        ok = false;
+        break;
+      }
+      double dl = 0.0, dl1 = 0.0, el = 0.0, dm = 0.0;
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        if (t == l) {
+          dl = d[t];
+          el = e[t];
+        }
+        if (t == l + 1) dl1 = d[t];
+        if (t == ms) dm = d[t];
+      }
+      double g = (dl1 - dl) / (2.0 * el);
+      double r = sqrt(fma(g, g, 1.0));
+      g = dm - dl + el / (g + copysign(r, g));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      bool under = false;
+#pragma unroll
+      for (int i = NM - 2; i >= 0; --i) {
+        if (i >= ms) continue;
+        if (i < l || under) break;
+        const double f = sn * e[i], b = cs * e[i];
+        const double q = fma(f, f, g * g);
+        const bool bad = !(q > 0.0);
+        const double rinv = bad ? 0.0 : rsqrt(q);
+        r = q * rinv;
+        e[i + 1] = r;
+        sn = f * rinv;
+        cs = bad ? 1.0 : g * rinv;
+        g = d[i + 1] - p;
+        r = fma(d[i] - g, sn, 2.0 * cs * b);
+        p = sn * r;
+        d[i + 1] = g + p;
+        g = fma(cs, r, -b);
+        const double zf = z[i + 1];
+        z[i + 1] = fma(sn, z[i], cs * zf);
+        z[i] = fma(cs, z[i], -sn * zf);
+        under = __builtin_amdgcn_readfirstlane((int)bad) != 0;
+      }
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        if (!under && t == l) {
+          d[t] -= p;
+          e[t] = g;
+        }
+        if (t == ms) e[t] = 0.0;
+      }
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t)
+      if (t < n) ev[t] = d[t];
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// 3. eigenvectors, spectral weights and pattern rows
+template <int NM, bool FB>
+__device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, double* sm) {
+  constexpr int LD = NM + 1;
+  const int lane = threadIdx.x;
+  const int n = a.nu_eff_in[slot];
+  const int j = a.cols[slot];
+  const int nuo = a.nu;
+  const int64_t oi = a.out_by_slot ? slot : (int64_t)j;  // output row
+  if (n <= 0 || n > NM) {
+    for (int k = lane; k < nuo; k += ETPB) {
+      a.eps[oi * nuo + k] = 0.0;
+      a.w[oi * nuo + k] = 0.0;
+    }
+    if (lane == 0) a.nu_eff_out[oi] = 0;
+    return;
+  }
+  double* T = sm;              // NM x LD: rows of Z, then the reflectors
+  double* Lm = T + NM * LD;    // NM x LD: L, zero padded
+  double* uu = Lm + NM * LD;   // row l of Q
+  double* s0 = uu + NM;        // s e_1
+  double* li = s0 + NM;        // 1 / L_ii
+  double* ev = li + NM;        // eigenvalues (unsorted)
+  const double* hL = a.hs + slot * (int64_t)(2 * NM * NM);
+  const double* hV = hL + NM * NM;
+  const double* tr = a.trid + slot * (int64_t)(4 * NM);
+
+  for (int idx = lane; idx < NM * NM; idx += ETPB) {
+    const int i = idx / NM, k = idx - (idx / NM) * NM;
+    Lm[i * LD + k] = (i < n && k < n) ? hL[i * NM + k] : 0.0;
+  }
+  if (lane < NM) {
+    uu[lane] = (lane < n) ? a.urow[slot * (int64_t)NM + lane] : 0.0;
+    s0[lane] = (lane < n) ? tr[3 * NM + lane] : 0.0;
+    li[lane] = (lane < n) ? 1.0 / hL[lane * NM + lane] : 0.0;
+  }
+
+  // ---- Z_T: rows of the identity, rotated
+  double z[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) z[t] = (t == lane) ? 1.0 : 0.0;
+  if (!FB) {
+    const int nsw = a.qlst[slot];
+    const double2* rec = reinterpret_cast<const double2*>(a.rot) + slot * (int64_t)a.rec_cap;
+    const int32_t* sw = a.sweep + slot * (int64_t)a.sweep_cap;
+    int ptr = 0;
+    for (int q = 0; q < nsw; ++q) {
+      const int hdr = sw[q];
+      const int ms = hdr >> 8, cnt = hdr & 255;
+      const int lo = ms - cnt;
+      // lane t holds the rotation of the plane (t, t+1); the sweep ran t = ms-1 down to lo
+      double2 rt = make_double2(0.0, 1.0);
+      if (lane < ms && lane >= lo) rt = rec[ptr + (ms - 1 - lane)];
+      ptr += cnt;
+#pragma unroll
+      for (int i = NM - 2; i >= 0; --i) {
+        if (i < ms && i >= lo) {
+          const double sn = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(rt.x), i),
+                                             __builtin_amdgcn_readlane(__double2loint(rt.x), i));
+          const double cs = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(rt.y), i),
+                                             __builtin_amdgcn_readlane(__double2loint(rt.y), i));
+          const double zf = z[i + 1];
+          z[i + 1] = fma(sn, z[i], cs * zf);
+          z[i] = fma(cs, z[i], -sn * zf);
+        }
+      }
+    }
+    if (lane < n) ev[lane] = a.evu[slot * (int64_t)NM + lane];
+  } else {
+    if (!ql_wave<NM>(tr, n, z, ev, lane) && lane == 0) atomicOr(a.err, (int)KERR_NOCONV);
+  }
+  if (lane < NM) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t) T[lane * LD + t] = z[t];
+  }
+  __syncthreads();
+  // ---- rank of eigenvalue `lane` (ascending, ties by index)
+  int rank = lane;
+  double ek = 0.0;
+  if (lane < n) {
+    ek = ev[lane];
+    rank = 0;
     for (int q2 = 0; q2 < n; ++q2) {
       const double f = ev[q2];
-      rank += (f < e || (f == e && q2 < k)) ? 1 : 0;
+      rank += (f < ek || (f == ek && q2 < lane)) ? 1 : 0;
     }
-    perm[rank] = k;
   }
-  // back substitution L^T c = V, column by column (into A)
-  for (int col = lane; col < n; col += ETPB) {
-    for (int i = m - 1; i >= 0; --i) {
-      double x = V[i * ld + col];
-      for (int p = i + 1; p < m; ++p) x -= L[p * ld + i] * A[p * ld + col];
-      A[i * ld + col] = x / L[i * ld + i];
-    }
+  // ---- column `lane` of Z_T
+  double y[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) y[t] = (lane < NM) ? T[t * LD + lane] : 0.0;
+  __syncthreads();
+  for (int idx = lane; idx < NM * NM; idx += ETPB) {
+    const int k = idx / NM, i = idx - (idx / NM) * NM;
+    T[k * LD + i] = (k + 2 < n && i < n) ? hV[k * NM + i] : 0.0;
   }
   __syncthreads();
-
+  // ---- y = P_0 P_1 ... P_{n-3} y
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = tr[2 * NM + k];
+    const double* vk = T + k * LD;
+    double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < NM; t += 2) {
+      r0 = fma(vk[t], y[t], r0);
+      if (t + 1 < NM) r1 = fma(vk[t + 1], y[t + 1], r1);
+    }
+    const double r = beta * (r0 + r1);
+#pragma unroll
+    for (int t = 0; t < NM; ++t) y[t] = fma(-r, vk[t], y[t]);
+  }
+  // ---- c = L^-T y (back substitution from the last row)
+#pragma unroll
+  for (int i = NM - 1; i >= 0; --i) {
+    double x = y[i];
+#pragma unroll
+    for (int p = i + 1; p < NM; ++p) x = fma(-Lm[p * LD + i], y[p], x);
+    y[i] = x * li[i];
+    __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight to one row
+  }
   // ---- d = c^T u, g = c^T s e_1, w = 2 d g
-  for (int k = lane; k < n; k += ETPB) {
-    double d = 0.0, g = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double cik = A[i * ld + k];
-      d = fma(uu[i], cik, d);
-      g = fma(s0[i], cik, g);
-    }
-    dv[k] = d;
-    gv[k] = g;
+  double dk = 0.0, gk = 0.0;
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    dk = fma(uu[t], y[t], dk);
+    gk = fma(s0[t], y[t], gk);
   }
-  __syncthreads();
-  for (int rk = lane; rk < nuo; rk += ETPB) {
-    double e = 0.0, wk = 0.0;
-    if (rk < n) {
-      const int k = perm[rk];
-      e = ev[k];
-      wk = G_SPIN * dv[k] * gv[k];
-      if (!isfinite(e) || !isfinite(wk)) atomicOr(a.err, (int)KERR_NONFINITE);
-    }
-    a.eps[oi * nuo + rk] = e;
-    a.w[oi * nuo + rk] = wk;
+  const double wk = G_SPIN * dk * gk;
+  if (lane < n) {
+    if (!isfinite(ek) || !isfinite(wk)) atomicOr(a.err, (int)KERR_NONFINITE);
+    a.eps[oi * nuo + rank] = ek;
+    a.w[oi * nuo + rank] = wk;
+  } else if (lane < nuo) {
+    a.eps[oi * nuo + lane] = 0.0;
+    a.w[oi * nuo + lane] = 0.0;
   }
   if (lane == 0) a.nu_eff_out[oi] = n;
 
-  // ---- P = (Q_pat c) diag(d), columns in ascending eigenvalue order
+  // ---- P = (Q_pat c) diag(d): row p, column rank(k)
   if (a.P) {
     const int np = a.npat[slot];
     const int64_t base = a.pmode ? a.rowptr[j] : slot * (int64_t)a.pat_stride;
-    const double* qp = a.qpat + slot * (int64_t)a.pat_stride * cap;
-    for (int rk = lane; rk < nuo; rk += ETPB) {
-      const int k = rk < n ? perm[rk] : 0;
-      const double dk = rk < n ? dv[k] : 0.0;
-      for (int p = 0; p < np; ++p) {
-        const double* qrow = qp + (int64_t)p * cap;
-        double y = 0.0;
-        if (rk < n)
-          for (int i = 0; i < n; ++i) y = fma(qrow[i], A[i * ld + k], y);
-        a.P[(base + p) * nuo + rk] = y * dk;
+    const double* qp = a.qpat + slot * (int64_t)a.pat_stride * NM;
+    for (int p = 0; p < np; ++p) {
+      const double* qrow = qp + (int64_t)p * NM;
+      double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < NM; t += 2) {
+        y0 = fma(qrow[t], y[t], y0);
+        if (t + 1 < NM) y1 = fma(qrow[t + 1], y[t + 1], y1);
       }
+      if (lane < nuo) a.P[(base + p) * nuo + rank] = (lane < n) ? (y0 + y1) * dk : 0.0;
     }
   }
 }
 
+template <int NM>
+__global__ __launch_bounds__(ETPB) void vec_kernel(EigArgs a) {
+  extern __shared__ double sm[];
+  const int64_t slot = blockIdx.x;
+  if (slot >= a.ncols) return;
+  const int n = a.nu_eff_in[slot];
+  if (n > 0 && n <= NM && a.qlst[slot] < 0) return;  // left to the fallback kernel
+  vectors_column<NM, false>(a, slot, sm);
+}
+
+template <int NM>
+__global__ __launch_bounds__(ETPB) void vec_fallback_kernel(EigArgs a) {
+  extern __shared__ double sm[];
+  const int cnt = *a.fb_count;
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+    vectors_column<NM, true>(a, a.fb_list[q], sm);
+    __syncthreads();
+  }
+}
+
+template <int NM>
+static hipError_t launch_eig_nm(const EigArgs& a, hipStream_t s) {
+  const unsigned nb = (unsigned)a.ncols;
+  const size_t lds1 = (size_t)2 * NM * (NM + 1) * sizeof(double) + 3 * NM * sizeof(double) +
+                      4 * sizeof(int);
+  const size_t lds3 = (size_t)2 * NM * (NM + 1) * sizeof(double) + 4 * NM * sizeof(double);
+  hipLaunchKernelGGL(tri_kernel<NM>, dim3(nb), dim3(ETPB), lds1, s, a);
+  hipError_t e = launch_fill_i32(a.fb_count, 1, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ql_kernel<NM>, dim3((nb + ETPB - 1) / ETPB), dim3(ETPB), 0, s, a);
+  hipLaunchKernelGGL(vec_kernel<NM>, dim3(nb), dim3(ETPB), lds3, s, a);
+  hipLaunchKernelGGL(vec_fallback_kernel<NM>, dim3(std::min(nb, 256u)), dim3(ETPB), lds3, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_eig(const EigArgs& a, hipStream_t s) {
   if (a.ncols <= 0) return hipSuccess;
-  const int m = a.nu + (a.nu & 1);
-  const size_t lds = (size_t)3 * m * (m + 1) * sizeof(double) + MAXP * sizeof(double2) +
-                     5 * 64 * sizeof(double) + MAXP * sizeof(int2) + (64 + 4) * sizeof(int) +
-                     (MAXP * (MAXP + 1) / 2) * sizeof(int2);
-  hipLaunchKernelGGL(eig_kernel, dim3((unsigned)a.ncols), dim3(ETPB), lds, s, a);
-  return hipGetLastError();
+  switch (a.cap) {
+    case 12: return launch_eig_nm<12>(a, s);
+    case 20: return launch_eig_nm<20>(a, s);
+    case 30: return launch_eig_nm<30>(a, s);
+    case 40: return launch_eig_nm<40>(a, s);
+    case 48: return launch_eig_nm<48>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // rho = 2 P f, pi = 2 P (f eps) on the pattern of each column (pass 2)

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mag.h"
+#include "mag.h"
 
 namespace mag {
 
@@ -30,6 +30,7 @@ enum KernelError : int {
   KERR_CAPACITY = 8,    // a fixed-size buffer would overflow
   KERR_LAYOUT = 16,     // CSR not block-complete
   KERR_BRACKET = 32,    // no sign change of N(mu) - N_e in the bracket
+  KERR_NOCONV = 64,     // projected eigensolver hit its iteration limit
 };
 
 struct DevBuf {
@@ -99,7 +100,7 @@ struct KrylovArgs {
 };
 
 struct EigArgs {
-  const double* hs;
+  double* hs;                 // projected pencils; overwritten by the reduction
   const double* urow;
   const double* qpat;
   const int32_t* nu_eff_in;   // per slot
@@ -117,6 +118,16 @@ struct EigArgs {
   int pat_stride;
   int out_by_slot;            // 1: eps/w/nu_eff rows indexed by slot instead of column
   int32_t* err;
+  // eigensolver scratch, per slot
+  double* trid;               // 4 cap: d, e, beta of the tridiagonal; s e_1
+  double* evu;                // cap: eigenvalues in QL order
+  double* rot;                // 2 rec_cap: recorded plane rotations (sn, cs)
+  int32_t* sweep;             // sweep_cap: (ms << 8) | count of each QL sweep
+  int32_t* qlst;              // number of sweeps, or < 0: finished by the fallback kernel
+  int32_t* fb_list;           // slots for the fallback kernel
+  int32_t* fb_count;          // 1
+  int rec_cap;
+  int sweep_cap;
 };
 
 struct DensityArgs {
@@ -142,6 +153,8 @@ constexpr int KRYLOV_QUEUES = 8;  // one work queue per XCD
 int krylov_capacity(int nu);  // template capacity used for nu (0 if unsupported)
 int krylov_rows(int cap);  // largest cluster (orbitals) the kernel for cap holds
 hipError_t launch_eig(const EigArgs& a, hipStream_t s);
+int eig_rec_cap(int cap);
+int eig_sweep_cap(int cap);
 hipError_t launch_density(const DensityArgs& a, hipStream_t s);
 
 hipError_t launch_mu_init(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
@@ -250,6 +263,7 @@ struct mag_ctx {
   int nu = 0;
   mag::DevBuf eps, w, nu_eff, state, partials, P, rho, pi;
   mag::DevBuf k_hs, k_urow, k_qpat, k_nu, k_npat, k_cols, k_queue, k_qbeg, errflag;
+  mag::DevBuf k_trid, k_evu, k_rot, k_sweep, k_qlst, k_fbl, k_fbc;
   mag::DevBuf tmp_cols, tmp_off, tmp_out;
   int64_t batch_cols = 0;
   mag::MuState h_state{};
