@@ -1,11 +1,11 @@
 // Per-column Krylov growth and projection (hot path of the multiple Arnoldi
 // method: one Krylov subspace per column j of G = (zS - H)^-1, Eq. 1).
 //
-// One workgroup of 512 threads (8 waves, two per SIMD) owns one column
-// j = (J, alpha) at a time.  Its cluster C(J) is gathered in LDS as a local
-// block-CSR over the global 4x4-block matrices (prologue), then nu Krylov
-// steps run with the basis Q (n_C x nu) distributed over the registers of the
-// workgroup: thread t owns cluster rows t and t + 512.  Each step:
+// One workgroup of KTPB threads owns one column j = (J, alpha) at a time.
+// Its cluster C(J) is gathered in LDS as a local block-CSR over the global
+// 4x4-block matrices (prologue), then nu Krylov steps run with the basis Q
+// (n_C x nu) distributed over the registers of the workgroup: thread t owns
+// cluster rows t + r * KTPB, r < R.  Each step:
 //   w = H_C q_k, z = S_C q_k       one fused SpMV (shared pattern and gathers)
 //   h[:,k] = Q^T w, s[:,k] = Q^T z  projection, taken from the first
 //                                   Gram-Schmidt pass's dot products
