@@ -250,6 +250,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
   if (NORB * maxat > krylov_rows(cap))
     return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the Krylov kernel holds for this nu");
   const int ncu = device_count_cus(ctx->device);
+  const int cache_cap = krylov_cache_cap(cap, ctx->device);
   int schedule = job.schedule == MAG_SCHED_AUTO ? MAG_SCHED_PERSISTENT : job.schedule;
   ctx->stats.schedule_used = schedule;
 
@@ -279,6 +280,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
     ka.cap = cap;
     ka.pat_stride = pat_stride;
     ka.full = job.full;
+    ka.cache_cap = cache_cap;
 
     EigArgs ea{};
     ea.hs = ka.hs;

@@ -22,12 +22,16 @@
 // queue w % KRYLOV_QUEUES (workgroups are dealt to the XCDs round-robin, so a
 // queue's clusters share that XCD's L2) and steals from the others when its
 // own is empty.
+#include <algorithm>
+#include <cstdlib>
+
 #include "mag_internal.h"
 #include "wave.h"
 
 namespace mag {
 
 constexpr int ENT_MAX = CLUSTER_MAX * 24;  // local blocks of a cluster
+constexpr int CACHE_MAX = 640;             // cluster blocks held in LDS at most
 
 __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   int lo = 0, hi = n - 1;
@@ -41,6 +45,28 @@ __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   return -1;
 }
 
+// one row of a 4x4 H block and of the S block against the block column's x
+#define MAG_BLOCK_FMA1                 \
+  wa = fma(h01.x, x01.x, wa);          \
+  wa = fma(h01.y, x01.y, wa);          \
+  wa = fma(h23.x, x23.x, wa);          \
+  wa = fma(h23.y, x23.y, wa);          \
+  za = fma(s01.x, x01.x, za);          \
+  za = fma(s01.y, x01.y, za);          \
+  za = fma(s23.x, x23.x, za);          \
+  za = fma(s23.y, x23.y, za);
+// two blocks, the second into separate accumulators
+#define MAG_BLOCK_FMA                  \
+  MAG_BLOCK_FMA1                       \
+  wb = fma(g01.x, y01.x, wb);          \
+  wb = fma(g01.y, y01.y, wb);          \
+  wb = fma(g23.x, y23.x, wb);          \
+  wb = fma(g23.y, y23.y, wb);          \
+  zb = fma(t01.x, y01.x, zb);          \
+  zb = fma(t01.y, y01.y, zb);          \
+  zb = fma(t23.x, y23.x, zb);          \
+  zb = fma(t23.y, y23.y, zb);
+
 template <int NU, int R, int KTPB>
 __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   constexpr int KWAVES = KTPB / 64;
@@ -48,7 +74,11 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   constexpr int RED = 16 * NCH + 8;
   __shared__ int32_t s_atoms[CLUSTER_MAX];
   __shared__ int32_t s_lptr[CLUSTER_MAX + 1];
-  __shared__ uint2 s_ent[ENT_MAX];  // (global block, local column atom)
+  // local block-CSR entry: (block offset in the global block row << 8) | local column atom
+  __shared__ uint16_t s_ent[ENT_MAX];
+  __shared__ int32_t s_cblk[CACHE_MAX];  // global block of each cached entry
+  // the first cache_cap entries' H and S blocks, kept for all nu steps of the column
+  extern __shared__ double2 s_cache[];
   __shared__ int16_t s_pat[NC_MAX];
   __shared__ double s_x[NC_MAX];
   __shared__ double s_red[KWAVES][RED];
@@ -136,13 +166,16 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       __syncthreads();
       continue;
     }
+    const int ncache = min(nent, a.cache_cap);
     for (int i = tid; i < nat; i += KTPB) {
       const int I = s_atoms[i];
+      const int b0 = a.bptr[I];
       int e = s_lptr[i];
-      for (int b = a.bptr[I]; b < a.bptr[I + 1]; ++b) {
+      for (int b = b0; b < a.bptr[I + 1]; ++b) {
         const int kl = lds_find(s_atoms, nat, a.bcol[b]);
         if (kl >= 0) {
-          s_ent[e] = make_uint2((unsigned)b, (unsigned)kl);
+          s_ent[e] = (uint16_t)(((b - b0) << 8) | kl);
+          if (e < ncache) s_cblk[e] = b;
           ++e;
         }
       }
@@ -150,8 +183,13 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     __syncthreads();
     // pattern rows of column j: block row of J, in CSR order (block t, orbital)
     for (int t = tid; t < NORB * nbJ; t += KTPB) {
-      const int kl = (int)s_ent[s_lptr[jl] + (t >> 2)].y;
+      const int kl = (int)(s_ent[s_lptr[jl] + (t >> 2)] & 255);
       s_pat[NORB * kl + (t & 3)] = (int16_t)t;
+    }
+    {
+      const double2* bv2 = reinterpret_cast<const double2*>(a.bval);
+      for (int idx = tid; idx < ncache * 16; idx += KTPB)
+        s_cache[idx] = bv2[(int64_t)s_cblk[idx >> 4] * 16 + (idx & 15)];
     }
     const int ell = NORB * jl + alpha;
     for (int i = tid; i < nC; i += KTPB) s_x[i] = (i == ell) ? 1.0 : 0.0;
@@ -163,18 +201,23 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       for (int i = 0; i < NU; ++i) qv[rr][i] = 0.0;
       if (tid + KTPB * rr == ell) qv[rr][0] = 1.0;
     }
-    // row bookkeeping of this thread
-    int e_beg[R], e_end[R], r_off[R];
+    // row bookkeeping of this thread: entry range, the split between cached
+    // and streamed blocks, and the row's position inside its global blocks
+    int e_beg[R], e_mid[R], e_end[R], r_off[R];
+    const double* rowp[R];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int r = tid + KTPB * rr;
       e_beg[rr] = 0;
       e_end[rr] = 0;
       r_off[rr] = (r & 3) * 4;
+      rowp[rr] = a.bval;
       if (r < nC) {
         e_beg[rr] = s_lptr[r >> 2];
         e_end[rr] = s_lptr[(r >> 2) + 1];
+        rowp[rr] = a.bval + (int64_t)a.bptr[s_atoms[r >> 2]] * 32 + r_off[rr];
       }
+      e_mid[rr] = min(max(ncache, e_beg[rr]), e_end[rr]);
     }
     const int nu_max = min(a.nu, nC);
     int nu_eff = nu_max;
@@ -183,19 +226,41 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     __syncthreads();
 
     for (int k = 0; k < nu_max; ++k) {
-      // ---- fused SpMV: w = H_C q_k, z = S_C q_k (two blocks per iteration)
+      // ---- fused SpMV: w = H_C q_k, z = S_C q_k (two blocks per iteration);
+      // cached blocks come from LDS, the rest stream from L2/HBM
       double w[R], z[R];
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         double wa = 0.0, za = 0.0, wb = 0.0, zb = 0.0;
         const int ro = r_off[rr];
         int e = e_beg[rr];
-        const int e1 = e_end[rr];
+        const int em = e_mid[rr], e1 = e_end[rr];
+        for (; e + 1 < em; e += 2) {
+          const double2* c0p = s_cache + e * 16 + (ro >> 1);
+          const double2* c1p = c0p + 16;
+          const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
+          const double2 g01 = c1p[0], g23 = c1p[1], t01 = c1p[8], t23 = c1p[9];
+          const int k0 = NORB * (s_ent[e] & 255), k1 = NORB * (s_ent[e + 1] & 255);
+          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+          const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
+          const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
+          MAG_BLOCK_FMA
+        }
+        if (e < em) {
+          const double2* c0p = s_cache + e * 16 + (ro >> 1);
+          const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
+          const int k0 = NORB * (s_ent[e] & 255);
+          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+          MAG_BLOCK_FMA1
+          ++e;
+        }
+        const double* rp = rowp[rr];
         for (; e + 1 < e1; e += 2) {
-          const uint2 p0 = s_ent[e];
-          const uint2 p1 = s_ent[e + 1];
-          const double* b0 = a.bval + (int64_t)p0.x * 32 + ro;
-          const double* b1 = a.bval + (int64_t)p1.x * 32 + ro;
+          const unsigned p0 = s_ent[e], p1 = s_ent[e + 1];
+          const double* b0 = rp + (p0 >> 8) * 32;
+          const double* b1 = rp + (p1 >> 8) * 32;
           const double2 h01 = *reinterpret_cast<const double2*>(b0);
           const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
           const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
@@ -204,44 +269,24 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           const double2 g23 = *reinterpret_cast<const double2*>(b1 + 2);
           const double2 t01 = *reinterpret_cast<const double2*>(b1 + 16);
           const double2 t23 = *reinterpret_cast<const double2*>(b1 + 18);
-          const double2 x01 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y);
-          const double2 x23 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y + 2);
-          const double2 y01 = *reinterpret_cast<const double2*>(s_x + NORB * p1.y);
-          const double2 y23 = *reinterpret_cast<const double2*>(s_x + NORB * p1.y + 2);
-          wa = fma(h01.x, x01.x, wa);
-          wa = fma(h01.y, x01.y, wa);
-          wa = fma(h23.x, x23.x, wa);
-          wa = fma(h23.y, x23.y, wa);
-          za = fma(s01.x, x01.x, za);
-          za = fma(s01.y, x01.y, za);
-          za = fma(s23.x, x23.x, za);
-          za = fma(s23.y, x23.y, za);
-          wb = fma(g01.x, y01.x, wb);
-          wb = fma(g01.y, y01.y, wb);
-          wb = fma(g23.x, y23.x, wb);
-          wb = fma(g23.y, y23.y, wb);
-          zb = fma(t01.x, y01.x, zb);
-          zb = fma(t01.y, y01.y, zb);
-          zb = fma(t23.x, y23.x, zb);
-          zb = fma(t23.y, y23.y, zb);
+          const int k0 = NORB * (p0 & 255), k1 = NORB * (p1 & 255);
+          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+          const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
+          const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
+          MAG_BLOCK_FMA
         }
         if (e < e1) {
-          const uint2 p0 = s_ent[e];
-          const double* b0 = a.bval + (int64_t)p0.x * 32 + ro;
+          const unsigned p0 = s_ent[e];
+          const double* b0 = rp + (p0 >> 8) * 32;
           const double2 h01 = *reinterpret_cast<const double2*>(b0);
           const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
           const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
           const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
-          const double2 x01 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y);
-          const double2 x23 = *reinterpret_cast<const double2*>(s_x + NORB * p0.y + 2);
-          wa = fma(h01.x, x01.x, wa);
-          wa = fma(h01.y, x01.y, wa);
-          wa = fma(h23.x, x23.x, wa);
-          wa = fma(h23.y, x23.y, wa);
-          za = fma(s01.x, x01.x, za);
-          za = fma(s01.y, x01.y, za);
-          za = fma(s23.x, x23.x, za);
-          za = fma(s23.y, x23.y, za);
+          const int k0 = NORB * (p0 & 255);
+          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+          MAG_BLOCK_FMA1
         }
         w[rr] = wa + wb;
         z[rr] = za + zb;
@@ -472,8 +517,53 @@ template <int NU>
 static hipError_t launch_nu(const KrylovArgs& a, int grid, hipStream_t s) {
   constexpr int T = KrylovShape<NU>::TPB;
   constexpr int R = KrylovShape<NU>::R;
-  hipLaunchKernelGGL((krylov_kernel<NU, R, T>), dim3(grid), dim3(T), 0, s, a);
+  const size_t dyn = (size_t)a.cache_cap * 16 * sizeof(double2);
+  hipLaunchKernelGGL((krylov_kernel<NU, R, T>), dim3(grid), dim3(T), dyn, s, a);
   return hipGetLastError();
+}
+
+// blocks of a cluster that fit in the LDS left over by the kernel's static
+// arrays (one workgroup per CU, so the cache costs no occupancy)
+template <int NU>
+static int cache_cap_nu(int device) {
+  constexpr int T = KrylovShape<NU>::TPB;
+  constexpr int R = KrylovShape<NU>::R;
+  hipFuncAttributes attr{};
+  if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&krylov_kernel<NU, R, T>)) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const long avail = (long)lds_max - (long)attr.sharedSizeBytes - 256;
+  int cap = avail > 0 ? (int)(avail / (16 * (long)sizeof(double2))) : 0;
+  cap = std::min(cap, CACHE_MAX);
+  if (cap > 0 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&krylov_kernel<NU, R, T>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          cap * 16 * (int)sizeof(double2)) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cap;
+}
+
+int krylov_cache_cap(int cap, int device) {
+  const char* env = std::getenv("MAG_LDS_CACHE");
+  if (env && std::atoi(env) == 0) return 0;
+  switch (cap) {
+    case 12: return cache_cap_nu<12>(device);
+    case 20: return cache_cap_nu<20>(device);
+    case 30: return cache_cap_nu<30>(device);
+    case 40: return cache_cap_nu<40>(device);
+    case 48: return cache_cap_nu<48>(device);
+    default: return 0;
+  }
 }
 
 int krylov_capacity(int nu) {

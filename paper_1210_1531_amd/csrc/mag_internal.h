@@ -97,6 +97,7 @@ struct KrylovArgs {
   int cap;                 // NU capacity used for strides
   int pat_stride;          // rows per slot in qpat (PAT_MAX, or NC_MAX when full)
   int full;                // 1: write every cluster row of Q, not only the pattern
+  int cache_cap;           // cluster blocks kept in LDS for the whole column (dynamic LDS)
 };
 
 struct EigArgs {
@@ -151,7 +152,8 @@ struct DensityArgs {
 hipError_t launch_krylov(const KrylovArgs& a, int cap, int grid, hipStream_t s);
 constexpr int KRYLOV_QUEUES = 8;  // one work queue per XCD
 int krylov_capacity(int nu);  // template capacity used for nu (0 if unsupported)
-int krylov_rows(int cap);  // largest cluster (orbitals) the kernel for cap holds
+int krylov_rows(int cap);
+int krylov_cache_cap(int cap, int device);  // largest cluster (orbitals) the kernel for cap holds
 hipError_t launch_eig(const EigArgs& a, hipStream_t s);
 int eig_rec_cap(int cap);
 int eig_sweep_cap(int cap);
