@@ -312,11 +312,11 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             v[t] = ph;
             v[8 + t] = ps;
           }
-          reduce16(v);
-          if ((lane & 15) == 0) {
-            const int base = c * 16 + ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) s_red[wave][base + t] = v[t];
+          const double r16 = reduce16(v);
+          if ((lane & 3) == 0) {
+            const int idx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 +
+                            ((lane >> 2) & 1) * 2 + ((lane >> 3) & 1);
+            s_red[wave][c * 16 + idx] = r16;
           }
         }
       }
@@ -380,11 +380,10 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             }
             v[t] = p;
           }
-          reduce8(v);
-          if ((lane & 15) == 0) {
-            const int base = c * 8 + ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2;
-            s_red[wave][base] = v[0];
-            s_red[wave][base + 1] = v[1];
+          const double r8 = reduce8(v);
+          if ((lane & 7) == 0) {
+            const int idx = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+            s_red[wave][c * 8 + idx] = r8;
           }
         }
       }
@@ -438,12 +437,13 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][0];
         beta2 = acc;
       }
-      const double beta = sqrt(fmax(beta2, 0.0));
-      if (!(beta > a.breakdown * sqrt(ww1))) {
+      // breakdown: |w| <= tol |H q_k|, compared in squares
+      const double b2 = fmax(beta2, 0.0);
+      if (!(b2 > a.breakdown * a.breakdown * ww1)) {
         nu_eff = k + 1;
         break;
       }
-      const double inv = 1.0 / beta;
+      const double inv = rsqrt(b2);
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
       // q_{k+1} into its register column: k is uniform, so a switch on it is a

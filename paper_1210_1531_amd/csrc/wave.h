@@ -60,25 +60,66 @@ __device__ __forceinline__ double wave_allreduce(double x) {
   return row_allreduce(x);
 }
 
-// 16 values per lane -> afterwards v[t], t < 4, holds the wave total of value
-// 8 * b5 + 4 * b4 + t, where b5, b4 are bits 5 and 4 of the lane id
-__device__ __forceinline__ void reduce16(double* v) {
+// DPP move with a bank mask: lanes of the enabled banks (groups of four lanes
+// in a row) take src as permuted by CTRL, the other lanes keep old
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double dpp_bank(double old, double src) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(src), CTRL, 0xF,
+                                             BANKS, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(src), CTRL, 0xF,
+                                             BANKS, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_IDENTITY = 0xE4;  // quad_perm [0,1,2,3]
+constexpr int BANKS_B3 = 0xC;       // lanes with bit 3 set (banks 2, 3 of a row)
+constexpr int BANKS_NB3 = 0x3;
+constexpr int BANKS_B2 = 0xA;       // lanes with bit 2 set (banks 1, 3)
+constexpr int BANKS_NB2 = 0x5;
+
+// reduce-scatter of the pair (a, b) between lane i and its row mirror 15 - i
+// (which differs in bit 3): lanes with bit 3 clear return a(i) + a(15-i), the
+// others b(i) + b(15-i)
+__device__ __forceinline__ double rs_mirror(double a, double b) {
+  const double keep = dpp_bank<DPP_IDENTITY, BANKS_B3>(a, b);
+  double recv = dpp_bank<DPP_ROW_MIRROR, BANKS_NB3>(0.0, a);
+  recv = dpp_bank<DPP_ROW_MIRROR, BANKS_B3>(recv, b);
+  return keep + recv;
+}
+// the same between lane i and its half-row mirror (differs in bit 2)
+__device__ __forceinline__ double rs_half_mirror(double a, double b) {
+  const double keep = dpp_bank<DPP_IDENTITY, BANKS_B2>(a, b);
+  double recv = dpp_bank<DPP_ROW_HALF_MIRROR, BANKS_NB2>(0.0, a);
+  recv = dpp_bank<DPP_ROW_HALF_MIRROR, BANKS_B2>(recv, b);
+  return keep + recv;
+}
+
+// 16 values per lane -> the return value is the wave total of value
+// 8 b5 + 4 b4 + 2 b2 + b3 (b_n: bit n of the lane id), the same in each quad
+__device__ __forceinline__ double reduce16(double* v) {
 #pragma unroll
   for (int t = 0; t < 8; ++t) v[t] = swap32_add(v[t], v[t + 8]);
 #pragma unroll
   for (int t = 0; t < 4; ++t) v[t] = swap16_add(v[t], v[t + 4]);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) v[t] = row_allreduce(v[t]);
+  const double u0 = rs_mirror(v[0], v[1]);
+  const double u1 = rs_mirror(v[2], v[3]);
+  double r = rs_half_mirror(u0, u1);
+  r += dpp_f64<DPP_QUAD_XOR2>(r);
+  r += dpp_f64<DPP_QUAD_XOR1>(r);
+  return r;
 }
 
-// 8 values per lane -> v[t], t < 2, holds the total of value 4 * b5 + 2 * b4 + t
-__device__ __forceinline__ void reduce8(double* v) {
+// 8 values per lane -> the wave total of value 4 b5 + 2 b4 + b3, the same in
+// each group of eight lanes
+__device__ __forceinline__ double reduce8(double* v) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) v[t] = swap32_add(v[t], v[t + 4]);
 #pragma unroll
   for (int t = 0; t < 2; ++t) v[t] = swap16_add(v[t], v[t + 2]);
-#pragma unroll
-  for (int t = 0; t < 2; ++t) v[t] = row_allreduce(v[t]);
+  double r = rs_mirror(v[0], v[1]);
+  r += dpp_f64<DPP_ROW_HALF_MIRROR>(r);
+  r += dpp_f64<DPP_QUAD_XOR2>(r);
+  r += dpp_f64<DPP_QUAD_XOR1>(r);
+  return r;
 }
 
 // 32 values per lane -> v[t], t < 8, holds the total of value 16 * b5 + 8 * b4 + t
