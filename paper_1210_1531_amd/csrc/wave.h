@@ -18,10 +18,20 @@ constexpr int DPP_ROW_HALF_MIRROR = 0x141;
 constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
 constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
 
+// DPP move of a double: every lane is written, so no old value is needed
+// (a tied old operand would cost a register copy per use)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// DPP move writing only the lanes of the enabled banks; the others are left
+// undefined (callers overwrite them)
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double dpp_part(double src) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(src), CTRL, 0xF, BANKS, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(src), CTRL, 0xF, BANKS, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -80,16 +90,16 @@ constexpr int BANKS_NB2 = 0x5;
 // (which differs in bit 3): lanes with bit 3 clear return a(i) + a(15-i), the
 // others b(i) + b(15-i)
 __device__ __forceinline__ double rs_mirror(double a, double b) {
-  const double keep = dpp_bank<DPP_IDENTITY, BANKS_B3>(a, b);
-  double recv = dpp_bank<DPP_ROW_MIRROR, BANKS_NB3>(0.0, a);
+  double recv = dpp_part<DPP_ROW_MIRROR, BANKS_NB3>(a);
   recv = dpp_bank<DPP_ROW_MIRROR, BANKS_B3>(recv, b);
+  const double keep = dpp_bank<DPP_IDENTITY, BANKS_B3>(a, b);
   return keep + recv;
 }
 // the same between lane i and its half-row mirror (differs in bit 2)
 __device__ __forceinline__ double rs_half_mirror(double a, double b) {
-  const double keep = dpp_bank<DPP_IDENTITY, BANKS_B2>(a, b);
-  double recv = dpp_bank<DPP_ROW_HALF_MIRROR, BANKS_NB2>(0.0, a);
+  double recv = dpp_part<DPP_ROW_HALF_MIRROR, BANKS_NB2>(a);
   recv = dpp_bank<DPP_ROW_HALF_MIRROR, BANKS_B2>(recv, b);
+  const double keep = dpp_bank<DPP_IDENTITY, BANKS_B2>(a, b);
   return keep + recv;
 }
 
