@@ -42,7 +42,43 @@ def parse(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-column-launch baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a 512 MiB fill and device copy (HBM counter calibration)")
     return ap.parse_args(argv)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "krylov_kernel_traffic_c4096_vac5_nu30.md")
+KERNEL_SOURCES = ("paper_1210_1531_amd/csrc/krylov.hip", "paper_1210_1531_amd/csrc/wave.h",
+                  "paper_1210_1531_amd/csrc/mag_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per Krylov launch from the committed counter profile, or None
+    when the profile is missing or was taken on a different kernel source."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(struct, target_s):
@@ -215,7 +251,7 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "krylov_kernel",
             "launch_ms": t_k,
             "bytes_per_launch": per_launch_bytes,
@@ -223,6 +259,12 @@ def main(argv=None):
             "fp64_frac": fp64_tflops / FP64_PEAK_TFLOPS,
         },
     }
+    if args.copy_probe:
+        a = torch.full((64 * 1024 * 1024,), 1.0, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
     print(json.dumps(out), flush=True)

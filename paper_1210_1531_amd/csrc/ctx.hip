@@ -990,7 +990,9 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
 
   // ---- chemical potential and energies
   Timer t2(ctx->stream);
-  const int grid = std::min<int64_t>(1024, std::max<int64_t>(1, (M * nu + 2047) / 2048));
+  // two blocks per CU at most: each thread walks a few Ritz terms, and the
+  // last block's sum over the per-block partials stays short
+  const int grid = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M * nu + 255) / 256));
   ALLOC(ctx->partials, sizeof(double) * 64 * (size_t)grid);
   MuState h{};
   h.ne = opts->n_electrons;

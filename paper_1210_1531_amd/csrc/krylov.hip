@@ -344,12 +344,15 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         hcol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + (i & 7)];
         scol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + 8 + (i & 7)];
       }
+      // a single exit at the bottom of the step keeps the basis registers in
+      // place (each early exit would need its own copy of them)
+      bool go = (k + 1 < nu_max);
       if (!isfinite(ww1)) {
         if (tid == 0) atomicOr(a.err, (int)KERR_NONFINITE);
         nu_eff = k + 1;
-        break;
+        go = false;
       }
-      if (k == nu_max - 1) break;
+      if (go) {
 
       // ---- w -= Q h[:, k], then the second pass c = Q^T w (one sweep)
 #pragma unroll
@@ -441,39 +444,32 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       const double b2 = fmax(beta2, 0.0);
       if (!(b2 > a.breakdown * a.breakdown * ww1)) {
         nu_eff = k + 1;
-        break;
-      }
-      const double inv = rsqrt(b2);
+        go = false;
+      } else {
+        const double inv = rsqrt(b2);
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
-      // q_{k+1} into its register column: k is uniform, so a switch on it is a
-      // scalar branch and costs no vector instructions per column slot
-      switch (k + 1) {
-#define MAG_QSTORE(I)                                        \
-  case I:                                                    \
-    if (I < NU) {                                            \
-      _Pragma("unroll") for (int rr = 0; rr < R; ++rr) qv[rr][I < NU ? I : 0] = w[rr]; \
-    }                                                        \
-    break;
-        MAG_QSTORE(1) MAG_QSTORE(2) MAG_QSTORE(3) MAG_QSTORE(4) MAG_QSTORE(5) MAG_QSTORE(6)
-        MAG_QSTORE(7) MAG_QSTORE(8) MAG_QSTORE(9) MAG_QSTORE(10) MAG_QSTORE(11) MAG_QSTORE(12)
-        MAG_QSTORE(13) MAG_QSTORE(14) MAG_QSTORE(15) MAG_QSTORE(16) MAG_QSTORE(17) MAG_QSTORE(18)
-        MAG_QSTORE(19) MAG_QSTORE(20) MAG_QSTORE(21) MAG_QSTORE(22) MAG_QSTORE(23) MAG_QSTORE(24)
-        MAG_QSTORE(25) MAG_QSTORE(26) MAG_QSTORE(27) MAG_QSTORE(28) MAG_QSTORE(29) MAG_QSTORE(30)
-        MAG_QSTORE(31) MAG_QSTORE(32) MAG_QSTORE(33) MAG_QSTORE(34) MAG_QSTORE(35) MAG_QSTORE(36)
-        MAG_QSTORE(37) MAG_QSTORE(38) MAG_QSTORE(39) MAG_QSTORE(40) MAG_QSTORE(41) MAG_QSTORE(42)
-        MAG_QSTORE(43) MAG_QSTORE(44) MAG_QSTORE(45) MAG_QSTORE(46) MAG_QSTORE(47)
-#undef MAG_QSTORE
-        default:
-          break;
-      }
-      static_assert(NU <= 48, "basis store covers 48 columns");
+        for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
+        // q_{k+1} into its register column.  k is uniform, so each test is a
+        // scalar branch; testing bits of a mask keeps the compiler from turning
+        // the chain into a switch whose merge copies every column
+        const unsigned long long sel = 1ull << (k + 1);
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        const int r = tid + KTPB * rr;
-        if (r < nC) s_x[r] = w[rr];
+        for (int i = 1; i < NU; ++i) {
+          if (sel & (1ull << i)) {
+            __asm__ volatile("");  // keep the branch (no speculation into selects)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) qv[rr][i] = w[rr];
+          }
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          const int r = tid + KTPB * rr;
+          if (r < nC) s_x[r] = w[rr];
+        }
+      }
       }
       __syncthreads();
+      if (!go) break;
     }
 
     // ---- epilogue: nu_eff, row l of Q, and the pattern (or all) rows of Q
