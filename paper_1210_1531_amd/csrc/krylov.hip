@@ -32,6 +32,7 @@ namespace mag {
 
 constexpr int ENT_MAX = CLUSTER_MAX * 24;  // local blocks of a cluster
 constexpr int CACHE_MAX = 640;             // cluster blocks held in LDS at most
+constexpr int CSLOT = 17;                  // double2 per cached block (16 + bank pad)
 
 __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   int lo = 0, hi = n - 1;
@@ -166,7 +167,9 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       __syncthreads();
       continue;
     }
-    const int ncache = min(nent, a.cache_cap);
+    // cached entry e sits at e * 17 double2 (272 bytes): the 16-byte pad puts
+    // consecutive atoms of a wave on different LDS bank groups
+    const int ncache = min(nent, a.cache_cap * 16 / CSLOT);
     for (int i = tid; i < nat; i += KTPB) {
       const int I = s_atoms[i];
       const int b0 = a.bptr[I];
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     {
       const double2* bv2 = reinterpret_cast<const double2*>(a.bval);
       for (int idx = tid; idx < ncache * 16; idx += KTPB)
-        s_cache[idx] = bv2[(int64_t)s_cblk[idx >> 4] * 16 + (idx & 15)];
+        s_cache[(idx >> 4) * CSLOT + (idx & 15)] = bv2[(int64_t)s_cblk[idx >> 4] * 16 + (idx & 15)];
     }
     const int ell = NORB * jl + alpha;
     for (int i = tid; i < nC; i += KTPB) s_x[i] = (i == ell) ? 1.0 : 0.0;
@@ -236,8 +239,8 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         int e = e_beg[rr];
         const int em = e_mid[rr], e1 = e_end[rr];
         for (; e + 1 < em; e += 2) {
-          const double2* c0p = s_cache + e * 16 + (ro >> 1);
-          const double2* c1p = c0p + 16;
+          const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
+          const double2* c1p = c0p + CSLOT;
           const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
           const double2 g01 = c1p[0], g23 = c1p[1], t01 = c1p[8], t23 = c1p[9];
           const int k0 = NORB * (s_ent[e] & 255), k1 = NORB * (s_ent[e + 1] & 255);
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           MAG_BLOCK_FMA
         }
         if (e < em) {
-          const double2* c0p = s_cache + e * 16 + (ro >> 1);
+          const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
           const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
           const int k0 = NORB * (s_ent[e] & 255);
           const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
