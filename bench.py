@@ -233,6 +233,9 @@ def main(argv=None):
             "schedule": args.schedule,
             "workflow": args.workflow,
             "workflow_used": {0: "recompute", 1: "store"}[st["workflow_used"]],
+            "krylov_buckets": st["krylov_buckets"],
+            "krylov_threads": st["krylov_tpb"],
+            "autotune_ms": st["autotune_ms"],
             "step": "fwd (pass 1 + mu + energy) + bwd (pass 2 rho/pi + forces)",
         },
         "fwd_columns_per_s": M / (ms_fwd * 1e-3),

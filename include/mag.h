@@ -303,6 +303,9 @@ typedef struct {
   double t_eig_ms;         /* last pass 1: summed durations of the eigensolver launches */
   int32_t krylov_launches; /* Krylov kernel launches in the last pass 1 */
   int32_t workflow_used;   /* mag_workflow of the last solve (never AUTO) */
+  int32_t krylov_buckets;  /* cluster-size buckets (workgroup shapes) of the last pass 1 */
+  int32_t krylov_tpb;      /* threads per workgroup of the largest bucket's plan */
+  double autotune_ms;      /* time spent timing launch plans (first use of a shape) */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

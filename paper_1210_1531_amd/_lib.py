@@ -89,6 +89,9 @@ class MagStats(C.Structure):
         ("t_eig_ms", C.c_double),
         ("krylov_launches", C.c_int32),
         ("workflow_used", C.c_int32),
+        ("krylov_buckets", C.c_int32),
+        ("krylov_tpb", C.c_int32),
+        ("autotune_ms", C.c_double),
     ]
 
 

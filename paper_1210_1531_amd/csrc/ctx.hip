@@ -210,6 +210,126 @@ std::vector<int64_t> queue_ranges(const mag_ctx* ctx, const int32_t* cols, int64
   return beg;
 }
 
+// ---- Krylov launch plans and their tuning
+
+static size_t lds_per_cu(int device) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
+          hipSuccess ||
+      v <= 0) {
+    (void)hipGetLastError();
+    v = 65536;
+  }
+  return (size_t)v;
+}
+
+// largest block cache for `per_cu` workgroups of a shape on one CU (0 if the
+// cache is switched off or does not fit)
+static size_t cache_bytes(int shape, int per_cu, int device) {
+  const char* env = std::getenv("MAG_LDS_CACHE");
+  if (env && std::atoi(env) == 0) return 0;
+  const size_t slot = (size_t)CSLOT_BYTES;
+  const long share = (long)(lds_per_cu(device) / per_cu) - (long)krylov_static_lds(shape) - 512;
+  if (share < (long)slot) return 0;
+  size_t dyn = ((size_t)share / slot) * slot;
+  dyn = std::min(dyn, (size_t)krylov_cache_blocks((size_t)1 << 30) * slot);
+  while (dyn > 0 && krylov_occupancy(shape, dyn) < per_cu) dyn -= slot;
+  return dyn;
+}
+
+static KrylovPlan make_plan(int shape, int per_cu, int device) {
+  KrylovPlan p;
+  p.shape = shape;
+  p.per_cu = per_cu;
+  p.dyn = cache_bytes(shape, per_cu, device);
+  p.cache = krylov_cache_blocks(p.dyn);
+  return p;
+}
+
+// the plan of bucket b (default: its own shape, as many workgroups per CU as
+// fit, the LDS left over as block cache)
+KrylovPlan& krylov_plan(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shapes, int b, int ncu) {
+  (void)ncu;
+  const auto key = std::make_pair(shapes[b].cap, shapes[b].id);
+  auto it = ctx->kplans.find(key);
+  if (it != ctx->kplans.end()) return it->second;
+  const int occ = std::max(1, krylov_occupancy(shapes[b].id, 0));
+  KrylovPlan p = make_plan(shapes[b].id, occ, ctx->device);
+  const char* env = std::getenv("MAG_AUTOTUNE");
+  p.tuned = env && std::atoi(env) == 0;  // tuning off: keep the default
+  return ctx->kplans.emplace(key, p).first->second;
+}
+
+// Time the candidate plans of bucket b -- its own shape and every larger one,
+// each with 1 .. (occupancy) workgroups per CU and the largest block cache
+// that leaves them -- on a sample of the bucket's columns, and keep the
+// fastest.  Every candidate computes the same columns (the results do not
+// depend on the plan), so the sample's outputs are simply overwritten by the
+// real launch.
+int krylov_tune(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shapes, int b,
+                const KrylovArgs& ka, int64_t off, int64_t nb, int ncu,
+                const int32_t* hslots, const int32_t* hcols) {
+  KrylovPlan& plan = krylov_plan(ctx, shapes, b, ncu);
+  if (plan.tuned) return MAG_OK;
+  plan.tuned = true;
+  if (nb < ncu) return MAG_OK;  // too few columns to fill the device: keep the default
+  const int64_t S = std::min<int64_t>(nb, 4 * (int64_t)ncu);
+  // queue ranges over the sample, in the spare queue slot after the buckets
+  std::vector<int32_t> scols(S);
+  for (int64_t i = 0; i < S; ++i) scols[i] = hcols[hslots[i]];
+  const std::vector<int64_t> qb = queue_ranges(ctx, scols.data(), S);
+  int64_t* dq = ctx->k_qbeg.as<int64_t>() + (KRYLOV_QUEUES + 1) * (int64_t)shapes.size();
+  HIPCHK(hipMemcpyAsync(dq, qb.data(), sizeof(int64_t) * qb.size(), hipMemcpyHostToDevice,
+                        ctx->stream));
+  TRY(sync(ctx));
+  int32_t* dc = ctx->k_queue.as<int32_t>() + KRYLOV_QUEUES * (int64_t)shapes.size();
+
+  std::vector<KrylovPlan> cand;
+  for (int s2 = b; s2 < (int)shapes.size(); ++s2) {
+    const int occ = std::max(1, krylov_occupancy(shapes[s2].id, 0));
+    for (int pc = 1; pc <= occ; ++pc) cand.push_back(make_plan(shapes[s2].id, pc, ctx->device));
+  }
+  if (cand.size() < 2) return MAG_OK;  // nothing to choose
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  HIPCHK(hipEventCreate(&t0));
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return fail(ctx, MAG_EHIP, "hipEventCreate failed");
+  }
+  Timer tt(ctx->stream);
+  double best = 1e300;
+  for (const KrylovPlan& c : cand) {
+    KrylovArgs kt = ka;
+    kt.slots = ctx->k_slots.as<int32_t>() + off;
+    kt.ncols = S;
+    kt.cache_cap = c.cache;
+    kt.queue = dc;
+    kt.qbeg = dq;
+    kt.nqueue = KRYLOV_QUEUES;
+    const int grid = (int)std::min<int64_t>(S, (int64_t)ncu * c.per_cu);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch also loads the code object
+      HIPCHK(launch_fill_i32(dc, KRYLOV_QUEUES, 0, ctx->stream));
+      HIPCHK(hipEventRecord(t0, ctx->stream));
+      HIPCHK(launch_krylov(kt, c.shape, c.dyn, grid, ctx->stream));
+      HIPCHK(hipEventRecord(t1, ctx->stream));
+      HIPCHK(hipEventSynchronize(t1));
+      HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    }
+    const double us = 1e3 * ms / (double)S;
+    if (us < best) {
+      best = us;
+      plan = c;
+      plan.tuned = true;
+      plan.us_per_col = us;
+    }
+  }
+  ctx->stats.autotune_ms += tt.stop_ms();
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return MAG_OK;
+}
+
 int run_columns(mag_ctx* ctx, ColumnJob& job) {
   const int64_t n = (int64_t)job.cols_host.size();
   if (n == 0) return MAG_OK;
@@ -231,8 +351,6 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
   ALLOC(ctx->k_qpat, sizeof(double) * bsz * (size_t)pat_stride * cap);
   ALLOC(ctx->k_nu, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_npat, sizeof(int32_t) * bsz);
-  ALLOC(ctx->k_queue, sizeof(int32_t) * KRYLOV_QUEUES);
-  ALLOC(ctx->k_qbeg, sizeof(int64_t) * (KRYLOV_QUEUES + 1));
   ALLOC(ctx->k_trid, sizeof(double) * bsz * 4 * cap);
   ALLOC(ctx->k_evu, sizeof(double) * bsz * cap);
   ALLOC(ctx->k_rot, sizeof(double) * bsz * 2 * (size_t)rec_cap);
@@ -245,12 +363,25 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
     ALLOC(ctx->tmp_out, sizeof(double) * bsz * (size_t)pat_stride * job.nu);
     Pbuf = ctx->tmp_out.as<double>();
   }
-  int maxat = 1;
-  for (int64_t i = 0; i < n; ++i) maxat = std::max(maxat, ctx->h_clus_size[job.cols_host[i] >> 2]);
-  if (NORB * maxat > krylov_rows(cap))
-    return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the Krylov kernel holds for this nu");
+  // workgroup shapes for this nu and the bucket (shape index) of every column
+  std::vector<KrylovShapeInfo> shapes(8);
+  shapes.resize(std::min<int>(8, krylov_shapes(cap, shapes.data(), 8)));
+  std::sort(shapes.begin(), shapes.end(),
+            [](const KrylovShapeInfo& x, const KrylovShapeInfo& y) { return x.rows() < y.rows(); });
+  std::vector<int8_t> bucket(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int rows = NORB * ctx->h_clus_size[job.cols_host[i] >> 2];
+    int b = 0;
+    while (b < (int)shapes.size() && shapes[b].rows() < rows) ++b;
+    if (b == (int)shapes.size())
+      return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the Krylov kernel holds for this nu");
+    bucket[i] = (int8_t)b;
+  }
+  const int nbk = (int)shapes.size();
+  ALLOC(ctx->k_slots, sizeof(int32_t) * bsz);
+  ALLOC(ctx->k_queue, sizeof(int32_t) * KRYLOV_QUEUES * (nbk + 1));
+  ALLOC(ctx->k_qbeg, sizeof(int64_t) * (KRYLOV_QUEUES + 1) * (nbk + 1));
   const int ncu = device_count_cus(ctx->device);
-  const int cache_cap = krylov_cache_cap(cap, ctx->device);
   int schedule = job.schedule == MAG_SCHED_AUTO ? MAG_SCHED_PERSISTENT : job.schedule;
   ctx->stats.schedule_used = schedule;
 
@@ -280,7 +411,8 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
     ka.cap = cap;
     ka.pat_stride = pat_stride;
     ka.full = job.full;
-    ka.cache_cap = cache_cap;
+    ka.cache_cap = 0;
+    ka.slots = nullptr;
 
     EigArgs ea{};
     ea.hs = ka.hs;
@@ -321,7 +453,9 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
         k1.qpat = ka.qpat + q * (int64_t)pat_stride * cap;
         k1.nu_eff = ka.nu_eff + q;
         k1.npat = ka.npat + q;
-        HIPCHK(launch_krylov(k1, cap, 1, ctx->stream));
+        const KrylovPlan& pl = krylov_plan(ctx, shapes, bucket[i0 + q], ncu);
+        k1.cache_cap = pl.cache;
+        HIPCHK(launch_krylov(k1, pl.shape, pl.dyn, 1, ctx->stream));
         EigArgs e1 = ea;
         e1.hs = k1.hs;
         e1.urow = k1.urow;
@@ -339,19 +473,38 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
         HIPCHK(launch_eig(e1, ctx->stream));
       }
     } else {
-      int grid = (int)cnt;
-      if (schedule == MAG_SCHED_PERSISTENT) {
-        const std::vector<int64_t> qb = queue_ranges(ctx, job.cols_host.data() + i0, cnt);
-        HIPCHK(hipMemcpyAsync(ctx->k_qbeg.p, qb.data(), sizeof(int64_t) * qb.size(),
-                              hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(launch_fill_i32(ctx->k_queue.as<int32_t>(), KRYLOV_QUEUES, 0, ctx->stream));
-        ka.queue = ctx->k_queue.as<int32_t>();
-        ka.qbeg = ctx->k_qbeg.as<int64_t>();
-        ka.nqueue = KRYLOV_QUEUES;
-        const char* occ = std::getenv("MAG_PERSIST_PER_CU");
-        const int per_cu = occ ? std::max(1, std::atoi(occ)) : 1;
-        grid = (int)std::min<int64_t>(cnt, (int64_t)ncu * per_cu);
-        TRY(sync(ctx));  // the host range vector goes out of scope
+      // one launch per bucket of cluster sizes, each over its own slot list
+      // (spatial order kept) and, when persistent, its own queues
+      std::vector<int32_t> hslots;
+      std::vector<int64_t> hqbeg((size_t)(KRYLOV_QUEUES + 1) * nbk, 0);
+      std::vector<int64_t> boff(nbk + 1, 0);
+      for (int b = 0; b < nbk; ++b) {
+        boff[b] = (int64_t)hslots.size();
+        std::vector<int32_t> bcols;
+        for (int64_t q = 0; q < cnt; ++q)
+          if (bucket[i0 + q] == b) {
+            hslots.push_back((int32_t)q);
+            bcols.push_back(job.cols_host[i0 + q]);
+          }
+        if (!bcols.empty()) {
+          const std::vector<int64_t> qb = queue_ranges(ctx, bcols.data(), (int64_t)bcols.size());
+          std::copy(qb.begin(), qb.end(), hqbeg.begin() + (size_t)(KRYLOV_QUEUES + 1) * b);
+        }
+      }
+      boff[nbk] = (int64_t)hslots.size();
+      HIPCHK(hipMemcpyAsync(ctx->k_slots.p, hslots.data(), sizeof(int32_t) * hslots.size(),
+                            hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->k_qbeg.p, hqbeg.data(), sizeof(int64_t) * hqbeg.size(),
+                            hipMemcpyHostToDevice, ctx->stream));
+      TRY(sync(ctx));  // the host lists go out of scope
+      // plans (tuned on first use) before the timed launches
+      std::vector<const KrylovPlan*> plans(nbk, nullptr);
+      for (int b = 0; b < nbk; ++b) {
+        if (boff[b + 1] == boff[b]) continue;
+        plans[b] = &krylov_plan(ctx, shapes, b, ncu);
+        if (schedule == MAG_SCHED_PERSISTENT && !plans[b]->tuned)
+          TRY(krylov_tune(ctx, shapes, b, ka, boff[b], boff[b + 1] - boff[b], ncu,
+                          hslots.data() + boff[b], job.cols_host.data() + i0));
       }
       hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
       if (ctx->time_kernels) {
@@ -359,8 +512,37 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
         e1 = pool_event(ctx, 3 * timed + 1);
         e2 = pool_event(ctx, 3 * timed + 2);
       }
+      {
+        int used = 0, tpb = 0;
+        for (int b = 0; b < nbk; ++b)
+          if (plans[b]) {
+            ++used;
+            for (const KrylovShapeInfo& sh : shapes)
+              if (sh.id == plans[b]->shape) tpb = sh.tpb;
+          }
+        ctx->stats.krylov_buckets = used;
+        ctx->stats.krylov_tpb = tpb;
+      }
       if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
-      HIPCHK(launch_krylov(ka, cap, grid, ctx->stream));
+      for (int b = 0; b < nbk; ++b) {
+        const int64_t nb = boff[b + 1] - boff[b];
+        if (nb == 0) continue;
+        const KrylovPlan& pl = *plans[b];
+        KrylovArgs kb = ka;
+        kb.slots = ctx->k_slots.as<int32_t>() + boff[b];
+        kb.ncols = nb;
+        kb.cache_cap = pl.cache;
+        int grid = (int)nb;
+        if (schedule == MAG_SCHED_PERSISTENT) {
+          HIPCHK(launch_fill_i32(ctx->k_queue.as<int32_t>() + KRYLOV_QUEUES * b, KRYLOV_QUEUES, 0,
+                                 ctx->stream));
+          kb.queue = ctx->k_queue.as<int32_t>() + KRYLOV_QUEUES * b;
+          kb.qbeg = ctx->k_qbeg.as<int64_t>() + (KRYLOV_QUEUES + 1) * b;
+          kb.nqueue = KRYLOV_QUEUES;
+          grid = (int)std::min<int64_t>(nb, (int64_t)ncu * pl.per_cu);
+        }
+        HIPCHK(launch_krylov(kb, pl.shape, pl.dyn, grid, ctx->stream));
+      }
       if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
       HIPCHK(launch_eig(ea, ctx->stream));
       if (e2) {

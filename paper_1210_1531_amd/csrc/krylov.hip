@@ -5,7 +5,8 @@
 // Its cluster C(J) is gathered in LDS as a local block-CSR over the global
 // 4x4-block matrices (prologue), then nu Krylov steps run with the basis Q
 // (n_C x nu) distributed over the registers of the workgroup: thread t owns
-// cluster rows t + r * KTPB, r < R.  Each step:
+// cluster rows R t + r, r < R (so wave w always holds rows 64 R w .. 64 R w +
+// 64 R - 1 and the results do not depend on the workgroup size).  Each step:
 //   w = H_C q_k, z = S_C q_k       one fused SpMV (shared pattern and gathers)
 //   h[:,k] = Q^T w, s[:,k] = Q^T z  projection, taken from the first
 //                                   Gram-Schmidt pass's dot products
@@ -32,7 +33,7 @@ namespace mag {
 
 constexpr int ENT_MAX = CLUSTER_MAX * 24;  // local blocks of a cluster
 constexpr int CACHE_MAX = 640;             // cluster blocks held in LDS at most
-constexpr int CSLOT = 17;                  // double2 per cached block (16 + bank pad)
+constexpr int CSLOT = CSLOT_BYTES / 16;    // double2 per cached block (16 + bank pad)
 
 __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   int lo = 0, hi = n - 1;
@@ -78,7 +79,8 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   // local block-CSR entry: (block offset in the global block row << 8) | local column atom
   __shared__ uint16_t s_ent[ENT_MAX];
   __shared__ int32_t s_cblk[CACHE_MAX];  // global block of each cached entry
-  // the first cache_cap entries' H and S blocks, kept for all nu steps of the column
+  // the first H and S blocks of the cluster (prefix of the entry list), kept for
+  // all nu steps of the column
   extern __shared__ double2 s_cache[];
   __shared__ int16_t s_pat[NC_MAX];
   __shared__ double s_x[NC_MAX];
@@ -118,6 +120,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       slot = blockIdx.x;
     }
     if (slot >= a.ncols) break;
+    if (a.slots) slot = a.slots[slot];  // this launch covers a subset of the slots
 
     const int j = a.cols[slot];
     const int J = j >> 2;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     }
     // cached entry e sits at e * 17 double2 (272 bytes): the 16-byte pad puts
     // consecutive atoms of a wave on different LDS bank groups
-    const int ncache = min(nent, a.cache_cap * 16 / CSLOT);
+    const int ncache = min(nent, a.cache_cap);
     for (int i = tid; i < nat; i += KTPB) {
       const int I = s_atoms[i];
       const int b0 = a.bptr[I];
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     for (int rr = 0; rr < R; ++rr) {
 #pragma unroll
       for (int i = 0; i < NU; ++i) qv[rr][i] = 0.0;
-      if (tid + KTPB * rr == ell) qv[rr][0] = 1.0;
+      if (R * tid + rr == ell) qv[rr][0] = 1.0;
     }
     // row bookkeeping of this thread: entry range, the split between cached
     // and streamed blocks, and the row's position inside its global blocks
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     const double* rowp[R];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-      const int r = tid + KTPB * rr;
+      const int r = R * tid + rr;
       e_beg[rr] = 0;
       e_end[rr] = 0;
       r_off[rr] = (r & 3) * 4;
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         }
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
-          const int r = tid + KTPB * rr;
+          const int r = R * tid + rr;
           if (r < nC) s_x[r] = w[rr];
         }
       }
@@ -482,7 +485,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
     }
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-      const int r = tid + KTPB * rr;
+      const int r = R * tid + rr;
       if (r < nC) {
         if (r == ell) {
           double* u = a.urow + slot * (int64_t)cap;
@@ -503,66 +506,102 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   }
 }
 
-// Thread count and rows per thread: nu <= 30 fits one row per thread in 168
-// VGPRs (768 threads, three waves per SIMD, clusters up to 768 orbitals);
-// larger nu uses 512 threads with two rows each.
-template <int NU>
-struct KrylovShape {
-  static constexpr int TPB = NU <= 30 ? 768 : 512;
-  static constexpr int R = NU <= 30 ? 1 : 2;
+// Workgroup shapes.  nu <= 30 keeps one cluster row per thread (up to 168
+// VGPRs: three waves per SIMD); 256-, 512- and 768-thread workgroups hold
+// clusters of up to 64, 128 and 192 atoms.  nu = 40, 48 keep two rows per
+// thread (two waves per SIMD).  The library picks a shape per bucket of
+// cluster sizes (and times the candidates once, see run_columns).
+template <int NU, int R, int T>
+static const void* kfn() {
+  return reinterpret_cast<const void*>(&krylov_kernel<NU, R, T>);
+}
+
+static const KrylovShapeInfo kShapes[] = {
+    {12, 256, 1, nullptr}, {12, 512, 1, nullptr}, {12, 768, 1, nullptr},
+    {20, 256, 1, nullptr}, {20, 512, 1, nullptr}, {20, 768, 1, nullptr},
+    {30, 256, 1, nullptr}, {30, 512, 1, nullptr}, {30, 768, 1, nullptr},
+    {40, 256, 2, nullptr}, {40, 512, 2, nullptr},
+    {48, 256, 2, nullptr}, {48, 512, 2, nullptr},
 };
+constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
-template <int NU>
-static hipError_t launch_nu(const KrylovArgs& a, int grid, hipStream_t s) {
-  constexpr int T = KrylovShape<NU>::TPB;
-  constexpr int R = KrylovShape<NU>::R;
-  const size_t dyn = (size_t)a.cache_cap * 16 * sizeof(double2);
-  hipLaunchKernelGGL((krylov_kernel<NU, R, T>), dim3(grid), dim3(T), dyn, s, a);
-  return hipGetLastError();
+static const void* shape_fn(int id) {
+  switch (id) {
+    case 0: return kfn<12, 1, 256>();
+    case 1: return kfn<12, 1, 512>();
+    case 2: return kfn<12, 1, 768>();
+    case 3: return kfn<20, 1, 256>();
+    case 4: return kfn<20, 1, 512>();
+    case 5: return kfn<20, 1, 768>();
+    case 6: return kfn<30, 1, 256>();
+    case 7: return kfn<30, 1, 512>();
+    case 8: return kfn<30, 1, 768>();
+    case 9: return kfn<40, 2, 256>();
+    case 10: return kfn<40, 2, 512>();
+    case 11: return kfn<48, 2, 256>();
+    case 12: return kfn<48, 2, 512>();
+    default: return nullptr;
+  }
 }
 
-// blocks of a cluster that fit in the LDS left over by the kernel's static
-// arrays (one workgroup per CU, so the cache costs no occupancy)
-template <int NU>
-static int cache_cap_nu(int device) {
-  constexpr int T = KrylovShape<NU>::TPB;
-  constexpr int R = KrylovShape<NU>::R;
+int krylov_shapes(int cap, KrylovShapeInfo* out, int max_out) {
+  int n = 0;
+  for (int i = 0; i < kNumShapes; ++i) {
+    if (kShapes[i].cap != cap) continue;
+    if (n < max_out) {
+      out[n] = kShapes[i];
+      out[n].id = i;
+    }
+    ++n;
+  }
+  return n;
+}
+
+size_t krylov_static_lds(int id) {
   hipFuncAttributes attr{};
-  if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&krylov_kernel<NU, R, T>)) !=
-      hipSuccess) {
+  if (hipFuncGetAttributes(&attr, shape_fn(id)) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
-  int lds_max = 0;
-  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
-      hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  const long avail = (long)lds_max - (long)attr.sharedSizeBytes - 256;
-  int cap = avail > 0 ? (int)(avail / (16 * (long)sizeof(double2))) : 0;
-  cap = std::min(cap, CACHE_MAX);
-  if (cap > 0 &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&krylov_kernel<NU, R, T>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          cap * 16 * (int)sizeof(double2)) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  return cap;
+  return attr.sharedSizeBytes;
 }
 
-int krylov_cache_cap(int cap, int device) {
-  const char* env = std::getenv("MAG_LDS_CACHE");
-  if (env && std::atoi(env) == 0) return 0;
-  switch (cap) {
-    case 12: return cache_cap_nu<12>(device);
-    case 20: return cache_cap_nu<20>(device);
-    case 30: return cache_cap_nu<30>(device);
-    case 40: return cache_cap_nu<40>(device);
-    case 48: return cache_cap_nu<48>(device);
-    default: return 0;
+// cached blocks that `dyn` bytes of dynamic LDS hold
+int krylov_cache_blocks(size_t dyn) {
+  return std::min<int>(CACHE_MAX, (int)(dyn / (CSLOT * sizeof(double2))));
+}
+
+// workgroups of shape `id` that fit on one CU with `dyn` bytes of dynamic
+// LDS each (0 if the launch would not fit); also raises the kernel's dynamic
+// LDS limit to `dyn`
+int krylov_occupancy(int id, size_t dyn) {
+  const void* fn = shape_fn(id);
+  if (!fn) return 0;
+  // the kernel's dynamic LDS limit only ever rises, so a query never lowers
+  // it below what an earlier plan launches with
+  static size_t dyn_set[kNumShapes] = {};
+  if (dyn > dyn_set[id]) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    dyn_set[id] = dyn;
   }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kShapes[id].tpb, dyn) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+hipError_t launch_krylov(const KrylovArgs& a, int id, size_t dyn, int grid, hipStream_t s) {
+  const void* fn = shape_fn(id);
+  if (!fn || grid <= 0) return hipErrorInvalidValue;
+  KrylovArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kShapes[id].tpb), args, dyn, s);
 }
 
 int krylov_capacity(int nu) {
@@ -570,27 +609,6 @@ int krylov_capacity(int nu) {
   for (int c : caps)
     if (nu <= c) return c;
   return 0;
-}
-
-int krylov_rows(int cap) {  // cluster orbitals one workgroup can hold
-  switch (cap) {
-    case 12: return KrylovShape<12>::TPB * KrylovShape<12>::R;
-    case 20: return KrylovShape<20>::TPB * KrylovShape<20>::R;
-    case 30: return KrylovShape<30>::TPB * KrylovShape<30>::R;
-    case 40: return KrylovShape<40>::TPB * KrylovShape<40>::R;
-    default: return KrylovShape<48>::TPB * KrylovShape<48>::R;
-  }
-}
-
-hipError_t launch_krylov(const KrylovArgs& a, int cap, int grid, hipStream_t s) {
-  switch (cap) {
-    case 12: return launch_nu<12>(a, grid, s);
-    case 20: return launch_nu<20>(a, grid, s);
-    case 30: return launch_nu<30>(a, grid, s);
-    case 40: return launch_nu<40>(a, grid, s);
-    case 48: return launch_nu<48>(a, grid, s);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 }  // namespace mag

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "mag.h"
@@ -20,6 +21,7 @@ constexpr int BLOCKS_MAX = MAG_BLOCKS_MAX;
 constexpr int PAT_MAX = NORB * BLOCKS_MAX;      // pattern entries of one CSR row
 constexpr int NC_MAX = NORB * CLUSTER_MAX;      // cluster orbitals
 constexpr double G_SPIN = 2.0;
+constexpr int CSLOT_BYTES = 272;  // LDS bytes per cached H/S block (256 + bank pad)
 
 // error flags raised by kernels (bit mask in a device int)
 enum KernelError : int {
@@ -98,6 +100,26 @@ struct KrylovArgs {
   int pat_stride;          // rows per slot in qpat (PAT_MAX, or NC_MAX when full)
   int full;                // 1: write every cluster row of Q, not only the pattern
   int cache_cap;           // cluster blocks kept in LDS for the whole column (dynamic LDS)
+  const int32_t* slots;    // nullptr: list position = slot; else the slots of this launch
+};
+
+// how the Krylov columns of one bucket of cluster sizes are launched
+struct KrylovPlan {
+  int shape = -1;          // workgroup shape (index into the shape table)
+  size_t dyn = 0;          // dynamic LDS bytes per workgroup (block cache)
+  int cache = 0;           // cached blocks that dyn holds
+  int per_cu = 1;          // persistent workgroups per CU
+  bool tuned = false;      // timed against the other candidates
+  double us_per_col = 0.0; // measured time per column when tuned
+};
+
+struct KrylovShapeInfo {
+  int cap;   // nu capacity (template)
+  int tpb;   // threads per workgroup
+  int r;     // cluster rows per thread
+  const void* unused;
+  int id = -1;
+  int rows() const { return tpb * r; }
 };
 
 struct EigArgs {
@@ -149,11 +171,13 @@ struct DensityArgs {
 // --------------------------------------------------------------------------
 // launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
-hipError_t launch_krylov(const KrylovArgs& a, int cap, int grid, hipStream_t s);
+hipError_t launch_krylov(const KrylovArgs& a, int shape, size_t dyn_lds, int grid, hipStream_t s);
+int krylov_shapes(int cap, KrylovShapeInfo* out, int max_out);  // shapes for a nu capacity
+size_t krylov_static_lds(int shape);
+int krylov_cache_blocks(size_t dyn_lds);
+int krylov_occupancy(int shape, size_t dyn_lds);  // workgroups per CU (0: does not fit)
 constexpr int KRYLOV_QUEUES = 8;  // one work queue per XCD
 int krylov_capacity(int nu);  // template capacity used for nu (0 if unsupported)
-int krylov_rows(int cap);
-int krylov_cache_cap(int cap, int device);  // largest cluster (orbitals) the kernel for cap holds
 hipError_t launch_eig(const EigArgs& a, hipStream_t s);
 int eig_rec_cap(int cap);
 int eig_sweep_cap(int cap);
@@ -265,7 +289,9 @@ struct mag_ctx {
   int nu = 0;
   mag::DevBuf eps, w, nu_eff, state, partials, P, rho, pi;
   mag::DevBuf k_hs, k_urow, k_qpat, k_nu, k_npat, k_cols, k_queue, k_qbeg, errflag;
-  mag::DevBuf k_trid, k_evu, k_rot, k_sweep, k_qlst, k_fbl, k_fbc;
+  mag::DevBuf k_trid, k_evu, k_rot, k_sweep, k_qlst, k_fbl, k_fbc, k_slots;
+  // Krylov launch plan per (nu capacity, workgroup shape of the bucket)
+  std::map<std::pair<int, int>, mag::KrylovPlan> kplans;
   mag::DevBuf tmp_cols, tmp_off, tmp_out;
   int64_t batch_cols = 0;
   mag::MuState h_state{};
