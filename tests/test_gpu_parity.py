@@ -165,6 +165,52 @@ def test_sampled_columns_at_full_size_config2():
     assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
 
 
+@pytest.mark.parametrize("nu", [20, 30, 40])
+def test_sampled_columns_at_full_size_void_cell(nu):
+    # the 16x16x16 void cell: clusters from 61 to 164 atoms, so several
+    # workgroup shapes run in one pass (two rows per thread at nu = 40); a
+    # sample of columns (smallest, largest and random clusters) against the oracle
+    from oracle import krylov, neighbors
+    import gen
+    s = gen.make(3, nu=nu)
+    log(f"[config3 nu {nu}] {s.n_atoms} atoms")
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    st = ctx.stats()
+    log(f"[config3 nu {nu}] buckets {st['krylov_buckets']} autotune {st['autotune_ms']:.1f} ms")
+    eps, w, nu_eff = (np_(x) for x in ctx.spectra())
+    rho, _ = (np_(x) for x in ctx.density_matrix())
+    rowptr = np_(ctx._csr[0])
+    colind = np_(ctx._csr[1])
+    ptr, atoms = (np_(x) for x in ctx.get_clusters())
+    sizes = np.diff(ptr)
+    rng = np.random.default_rng(11 + nu)
+    atoms_pick = np.unique(np.concatenate([np.argsort(sizes)[:4], np.argsort(sizes)[-3:],
+                                           rng.choice(s.n_atoms, 6, replace=False)]))
+    worst = 0.0
+    for J in atoms_pick:
+        clus = neighbors.cluster_of(s.pos, s.cell, int(J), s.r_cluster)
+        np.testing.assert_array_equal(clus, atoms[ptr[J]:ptr[J + 1]])
+        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
+        jl = int(np.searchsorted(clus, J))
+        for a in range(4):
+            j = 4 * int(J) + a
+            res = krylov.column_mode_k(Hc, Sc, 4 * jl + a, s.nu)
+            assert res.nu_eff == nu_eff[j]
+            np.testing.assert_allclose(eps[j, :res.nu_eff], res.eps, rtol=0, atol=1e-9)
+            np.testing.assert_allclose(w[j, :res.nu_eff], res.w, rtol=0, atol=1e-10)
+            col, _ = krylov.density_column(res, mu, s.kT)
+            lo, hi = rowptr[j], rowptr[j + 1]
+            rows = np.searchsorted(clus, colind[lo:hi] // 4) * 4 + colind[lo:hi] % 4
+            worst = max(worst, np.abs(rho[lo:hi] - col[rows]).max())
+    log(f"[config3 nu {nu}] sampled {len(atoms_pick)} atoms (sizes {sizes.min()}-{sizes.max()}), "
+        f"max |d rho| {worst:.3e}")
+    assert worst <= RHO_TOL
+    sums = np.where(np.arange(w.shape[1])[None, :] < nu_eff[:, None], w, 0.0).sum(axis=1)
+    np.testing.assert_allclose(sums, 2.0, atol=1e-11)
+    assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
+
+
 def test_green_and_cluster_columns_match_oracle():
     from oracle import krylov, neighbors
     import gen
