@@ -184,6 +184,23 @@ def main(argv=None):
         torch.cuda.synchronize()
         rec = M / ((time.perf_counter() - t0) / n_rec)
 
+    # the forward solve captured in a HIP graph and replayed (when not the headline)
+    graph = None
+    if args.schedule != "graph":
+        gopts = dict(opts, schedule="graph")
+        ctx.solve(**gopts)  # eager solve + capture
+        ctx.solve(**gopts)
+        ctx.backward(1.0)
+        ctx.forces(sk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.solve(**gopts)
+            ctx.backward(1.0)
+            ctx.forces(sk)
+        torch.cuda.synchronize()
+        graph = M / ((time.perf_counter() - t0) / args.steps)
+
     # plain per-column launches (forward)
     plain = None
     if not args.no_plain:
@@ -240,6 +257,7 @@ def main(argv=None):
         },
         "fwd_columns_per_s": M / (ms_fwd * 1e-3),
         "fwdbwd_recompute_columns_per_s": rec,
+        "fwdbwd_graph_columns_per_s": graph,
         "fwd_ms": ms_fwd,
         "plain_fwd_columns_per_s": plain,
         "fwd_speedup_vs_plain": (M / (ms_fwd * 1e-3)) / plain if plain else None,

@@ -77,16 +77,24 @@ enum mag_workflow {
   MAG_WORKFLOW_AUTO = 2
 };
 
-/* Launch schedule of the per-column Krylov kernels.  PERSISTENT: one launch of
- * resident workgroups pulling columns (largest clusters first) from a device
- * queue.  GRID: one launch, one workgroup per column.  PLAIN: one launch per
- * column.  AUTO: the library's tuned choice.  Per-column results are
- * bitwise identical across schedules. */
+/* Launch schedule of the per-column Krylov kernels.  Columns are grouped into
+ * buckets by cluster size; each bucket runs in the workgroup shape and
+ * occupancy that the library timed fastest on first use.  PERSISTENT: per
+ * bucket, one launch of resident workgroups pulling columns from eight
+ * device queues of spatially contiguous columns (one per XCD, with
+ * stealing).  GRID: per bucket, one launch with one workgroup per column.
+ * PLAIN: one launch per column.  GRAPH: PERSISTENT launches, with the whole
+ * forward solve (Krylov passes, eigensolves, bisection for mu, energies)
+ * captured once in a HIP graph and replayed by later solves with the same
+ * system and options; the first call runs eagerly, and a graph is captured
+ * again whenever a device buffer it uses has moved.  AUTO: PERSISTENT.
+ * Per-column results are bitwise identical across schedules. */
 enum mag_schedule {
   MAG_SCHED_AUTO = 0,
   MAG_SCHED_PERSISTENT = 1,
   MAG_SCHED_GRID = 2,
-  MAG_SCHED_PLAIN = 3
+  MAG_SCHED_PLAIN = 3,
+  MAG_SCHED_GRAPH = 4
 };
 
 /* ---------------------------------------------------------------------- */

@@ -31,6 +31,7 @@ MAG_SCHED_AUTO = 0
 MAG_SCHED_PERSISTENT = 1
 MAG_SCHED_GRID = 2
 MAG_SCHED_PLAIN = 3
+MAG_SCHED_GRAPH = 4
 NORB = 4
 NU_MAX = 48
 CLUSTER_MAX = 192

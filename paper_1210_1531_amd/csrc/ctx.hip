@@ -23,13 +23,16 @@ int fail(mag_ctx* ctx, int code, const std::string& msg) {
       return fail(ctx, MAG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
   } while (0)
 
+// grow-only device allocation; a buffer that moves invalidates captured graphs
 #define ALLOC(buf, bytes)                                                                  \
   do {                                                                                     \
+    void* old_p_ = (buf).p;                                                                \
     if ((buf).reserve(bytes) != hipSuccess) {                                              \
       (void)hipGetLastError();                                                             \
       return fail(ctx, MAG_ENOMEM, std::string("device allocation of ") +                 \
                                        std::to_string((size_t)(bytes)) + " bytes failed"); \
     }                                                                                      \
+    if ((buf).p != old_p_) ++ctx->alloc_gen;                                               \
   } while (0)
 
 #define TRY(expr)                \
@@ -210,6 +213,79 @@ std::vector<int64_t> queue_ranges(const mag_ctx* ctx, const int32_t* cols, int64
   return beg;
 }
 
+// columns per chunk: the per-column scratch of a chunk stays within
+// MAG_SCRATCH_GB (default 8 GB)
+int64_t chunk_columns(const ColumnJob& job, int64_t n) {
+  const int cap = krylov_capacity(job.nu);
+  const int pat_stride = job.full ? NC_MAX : PAT_MAX;
+  const int rec_cap = eig_rec_cap(cap), sweep_cap = eig_sweep_cap(cap);
+  const size_t per_slot =
+      sizeof(double) * ((size_t)2 * cap * cap + cap + (size_t)pat_stride * cap) + 2 * sizeof(int32_t) +
+      sizeof(double) * ((size_t)5 * cap + 2 * (size_t)rec_cap) +
+      sizeof(int32_t) * ((size_t)sweep_cap + 2) +
+      (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0);
+  const char* env = std::getenv("MAG_SCRATCH_GB");
+  const double budget_gb = env ? std::atof(env) : 8.0;
+  int64_t bmax = (int64_t)(budget_gb * 1e9 / (double)per_slot);
+  if (bmax < 1) bmax = 1;
+  return std::min(n, bmax);
+}
+
+// workgroup shapes for the job's nu (by rows held) and the bucket of every column
+int column_buckets(mag_ctx* ctx, const ColumnJob& job, std::vector<KrylovShapeInfo>& shapes,
+                   std::vector<int8_t>& bucket) {
+  const int cap = krylov_capacity(job.nu);
+  shapes.resize(8);
+  shapes.resize(std::min<int>(8, krylov_shapes(cap, shapes.data(), 8)));
+  std::sort(shapes.begin(), shapes.end(),
+            [](const KrylovShapeInfo& x, const KrylovShapeInfo& y) { return x.rows() < y.rows(); });
+  const int64_t n = (int64_t)job.cols_host.size();
+  bucket.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int rows = NORB * ctx->h_clus_size[job.cols_host[i] >> 2];
+    int b = 0;
+    while (b < (int)shapes.size() && shapes[b].rows() < rows) ++b;
+    if (b == (int)shapes.size())
+      return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the Krylov kernel holds for this nu");
+    bucket[i] = (int8_t)b;
+  }
+  return MAG_OK;
+}
+
+// Slot lists of one chunk: the positions [0, cnt) grouped by bucket (in
+// chunk order, so each bucket stays spatially ordered), the bucket offsets,
+// and each bucket's queue ranges (KRYLOV_QUEUES + 1 entries per bucket).
+void chunk_lists(const mag_ctx* ctx, const int32_t* cols, const int8_t* bucket, int64_t cnt,
+                 int nbk, std::vector<int32_t>& hslots, std::vector<int64_t>& hqbeg,
+                 std::vector<int64_t>& boff) {
+  hslots.clear();
+  hqbeg.assign((size_t)(KRYLOV_QUEUES + 1) * nbk, 0);
+  boff.assign(nbk + 1, 0);
+  for (int b = 0; b < nbk; ++b) {
+    boff[b] = (int64_t)hslots.size();
+    std::vector<int32_t> bcols;
+    for (int64_t q = 0; q < cnt; ++q)
+      if (bucket[q] == b) {
+        hslots.push_back((int32_t)q);
+        bcols.push_back(cols[q]);
+      }
+    if (!bcols.empty()) {
+      const std::vector<int64_t> qb = queue_ranges(ctx, bcols.data(), (int64_t)bcols.size());
+      std::copy(qb.begin(), qb.end(), hqbeg.begin() + (size_t)(KRYLOV_QUEUES + 1) * b);
+    }
+  }
+  boff[nbk] = (int64_t)hslots.size();
+}
+
+// device column lists of every chunk of a captured solve
+struct GraphLists {
+  const int32_t* slots = nullptr;  // concatenated chunk lists
+  const int64_t* qbeg = nullptr;   // per (chunk, bucket): KRYLOV_QUEUES + 1
+  int32_t* queue = nullptr;        // per (chunk, bucket): KRYLOV_QUEUES counters
+  std::vector<std::vector<int64_t>> boff;  // host: per chunk, bucket offsets
+  std::vector<int64_t> slot_base;          // host: per chunk, offset into slots
+};
+
 // ---- Krylov launch plans and their tuning
 
 static size_t lds_per_cu(int device) {
@@ -330,22 +406,13 @@ int krylov_tune(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shapes, int b,
   return MAG_OK;
 }
 
-int run_columns(mag_ctx* ctx, ColumnJob& job) {
+int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
   const int64_t n = (int64_t)job.cols_host.size();
   if (n == 0) return MAG_OK;
   const int cap = krylov_capacity(job.nu);
   const int pat_stride = job.full ? NC_MAX : PAT_MAX;
   const int rec_cap = eig_rec_cap(cap), sweep_cap = eig_sweep_cap(cap);
-  const size_t per_slot =
-      sizeof(double) * ((size_t)2 * cap * cap + cap + (size_t)pat_stride * cap) + 2 * sizeof(int32_t) +
-      sizeof(double) * ((size_t)5 * cap + 2 * (size_t)rec_cap) +
-      sizeof(int32_t) * ((size_t)sweep_cap + 2) +
-      (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0);
-  const char* env = std::getenv("MAG_SCRATCH_GB");
-  const double budget_gb = env ? std::atof(env) : 8.0;
-  int64_t bmax = (int64_t)(budget_gb * 1e9 / (double)per_slot);
-  if (bmax < 1) bmax = 1;
-  const int64_t bsz = std::min(n, bmax);
+  const int64_t bsz = chunk_columns(job, n);
   ALLOC(ctx->k_hs, sizeof(double) * bsz * 2 * cap * cap);
   ALLOC(ctx->k_urow, sizeof(double) * bsz * cap);
   ALLOC(ctx->k_qpat, sizeof(double) * bsz * (size_t)pat_stride * cap);
@@ -364,25 +431,17 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
     Pbuf = ctx->tmp_out.as<double>();
   }
   // workgroup shapes for this nu and the bucket (shape index) of every column
-  std::vector<KrylovShapeInfo> shapes(8);
-  shapes.resize(std::min<int>(8, krylov_shapes(cap, shapes.data(), 8)));
-  std::sort(shapes.begin(), shapes.end(),
-            [](const KrylovShapeInfo& x, const KrylovShapeInfo& y) { return x.rows() < y.rows(); });
-  std::vector<int8_t> bucket(n);
-  for (int64_t i = 0; i < n; ++i) {
-    const int rows = NORB * ctx->h_clus_size[job.cols_host[i] >> 2];
-    int b = 0;
-    while (b < (int)shapes.size() && shapes[b].rows() < rows) ++b;
-    if (b == (int)shapes.size())
-      return fail(ctx, MAG_EUNSUPPORTED, "cluster larger than the Krylov kernel holds for this nu");
-    bucket[i] = (int8_t)b;
-  }
+  std::vector<KrylovShapeInfo> shapes;
+  std::vector<int8_t> bucket;
+  TRY(column_buckets(ctx, job, shapes, bucket));
   const int nbk = (int)shapes.size();
   ALLOC(ctx->k_slots, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_queue, sizeof(int32_t) * KRYLOV_QUEUES * (nbk + 1));
   ALLOC(ctx->k_qbeg, sizeof(int64_t) * (KRYLOV_QUEUES + 1) * (nbk + 1));
   const int ncu = device_count_cus(ctx->device);
-  int schedule = job.schedule == MAG_SCHED_AUTO ? MAG_SCHED_PERSISTENT : job.schedule;
+  int schedule = (job.schedule == MAG_SCHED_AUTO || job.schedule == MAG_SCHED_GRAPH)
+                     ? MAG_SCHED_PERSISTENT
+                     : job.schedule;
   ctx->stats.schedule_used = schedule;
 
   size_t timed = 0;
@@ -476,38 +535,38 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
       // one launch per bucket of cluster sizes, each over its own slot list
       // (spatial order kept) and, when persistent, its own queues
       std::vector<int32_t> hslots;
-      std::vector<int64_t> hqbeg((size_t)(KRYLOV_QUEUES + 1) * nbk, 0);
-      std::vector<int64_t> boff(nbk + 1, 0);
-      for (int b = 0; b < nbk; ++b) {
-        boff[b] = (int64_t)hslots.size();
-        std::vector<int32_t> bcols;
-        for (int64_t q = 0; q < cnt; ++q)
-          if (bucket[i0 + q] == b) {
-            hslots.push_back((int32_t)q);
-            bcols.push_back(job.cols_host[i0 + q]);
-          }
-        if (!bcols.empty()) {
-          const std::vector<int64_t> qb = queue_ranges(ctx, bcols.data(), (int64_t)bcols.size());
-          std::copy(qb.begin(), qb.end(), hqbeg.begin() + (size_t)(KRYLOV_QUEUES + 1) * b);
+      std::vector<int64_t> hqbeg, boff;
+      const int32_t* dslots = ctx->k_slots.as<int32_t>();
+      const int64_t* dqbeg = ctx->k_qbeg.as<int64_t>();
+      int32_t* dqueue = ctx->k_queue.as<int32_t>();
+      std::vector<const KrylovPlan*> plans(nbk, nullptr);
+      if (gl) {  // captured solve: lists are resident, plans already tuned
+        const size_t c = (size_t)(i0 / bsz);
+        boff = gl->boff[c];
+        dslots = gl->slots + gl->slot_base[c];
+        dqbeg = gl->qbeg + (int64_t)c * nbk * (KRYLOV_QUEUES + 1);
+        dqueue = gl->queue + (int64_t)c * nbk * KRYLOV_QUEUES;
+        for (int b = 0; b < nbk; ++b)
+          if (boff[b + 1] > boff[b]) plans[b] = &krylov_plan(ctx, shapes, b, ncu);
+      } else {
+        chunk_lists(ctx, job.cols_host.data() + i0, bucket.data() + i0, cnt, nbk, hslots, hqbeg,
+                    boff);
+        HIPCHK(hipMemcpyAsync(ctx->k_slots.p, hslots.data(), sizeof(int32_t) * hslots.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(ctx->k_qbeg.p, hqbeg.data(), sizeof(int64_t) * hqbeg.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+        TRY(sync(ctx));  // the host lists go out of scope
+        // plans (tuned on first use) before the timed launches
+        for (int b = 0; b < nbk; ++b) {
+          if (boff[b + 1] == boff[b]) continue;
+          plans[b] = &krylov_plan(ctx, shapes, b, ncu);
+          if (schedule == MAG_SCHED_PERSISTENT && !plans[b]->tuned)
+            TRY(krylov_tune(ctx, shapes, b, ka, boff[b], boff[b + 1] - boff[b], ncu,
+                            hslots.data() + boff[b], job.cols_host.data() + i0));
         }
       }
-      boff[nbk] = (int64_t)hslots.size();
-      HIPCHK(hipMemcpyAsync(ctx->k_slots.p, hslots.data(), sizeof(int32_t) * hslots.size(),
-                            hipMemcpyHostToDevice, ctx->stream));
-      HIPCHK(hipMemcpyAsync(ctx->k_qbeg.p, hqbeg.data(), sizeof(int64_t) * hqbeg.size(),
-                            hipMemcpyHostToDevice, ctx->stream));
-      TRY(sync(ctx));  // the host lists go out of scope
-      // plans (tuned on first use) before the timed launches
-      std::vector<const KrylovPlan*> plans(nbk, nullptr);
-      for (int b = 0; b < nbk; ++b) {
-        if (boff[b + 1] == boff[b]) continue;
-        plans[b] = &krylov_plan(ctx, shapes, b, ncu);
-        if (schedule == MAG_SCHED_PERSISTENT && !plans[b]->tuned)
-          TRY(krylov_tune(ctx, shapes, b, ka, boff[b], boff[b + 1] - boff[b], ncu,
-                          hslots.data() + boff[b], job.cols_host.data() + i0));
-      }
       hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-      if (ctx->time_kernels) {
+      if (ctx->time_kernels && !gl) {
         e0 = pool_event(ctx, 3 * timed + 0);
         e1 = pool_event(ctx, 3 * timed + 1);
         e2 = pool_event(ctx, 3 * timed + 2);
@@ -529,15 +588,14 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
         if (nb == 0) continue;
         const KrylovPlan& pl = *plans[b];
         KrylovArgs kb = ka;
-        kb.slots = ctx->k_slots.as<int32_t>() + boff[b];
+        kb.slots = dslots + boff[b];
         kb.ncols = nb;
         kb.cache_cap = pl.cache;
         int grid = (int)nb;
         if (schedule == MAG_SCHED_PERSISTENT) {
-          HIPCHK(launch_fill_i32(ctx->k_queue.as<int32_t>() + KRYLOV_QUEUES * b, KRYLOV_QUEUES, 0,
-                                 ctx->stream));
-          kb.queue = ctx->k_queue.as<int32_t>() + KRYLOV_QUEUES * b;
-          kb.qbeg = ctx->k_qbeg.as<int64_t>() + (KRYLOV_QUEUES + 1) * b;
+          HIPCHK(launch_fill_i32(dqueue + KRYLOV_QUEUES * b, KRYLOV_QUEUES, 0, ctx->stream));
+          kb.queue = dqueue + KRYLOV_QUEUES * b;
+          kb.qbeg = dqbeg + (KRYLOV_QUEUES + 1) * b;
           kb.nqueue = KRYLOV_QUEUES;
           grid = (int)std::min<int64_t>(nb, (int64_t)ncu * pl.per_cu);
         }
@@ -576,7 +634,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job) {
       da.pi = job.pi;
       HIPCHK(launch_density(da, ctx->stream));
     }
-    if (i0 + cnt < n) TRY(sync(ctx));  // the next chunk reuses the scratch
+    // the next chunk reuses the scratch: stream order keeps it safe
   }
   if (ctx->time_kernels) {
     TRY(sync(ctx));
@@ -603,7 +661,7 @@ int check_opts(mag_ctx* ctx, const mag_opts* o) {
   if (o->workflow != MAG_WORKFLOW_RECOMPUTE && o->workflow != MAG_WORKFLOW_STORE &&
       o->workflow != MAG_WORKFLOW_AUTO)
     return fail(ctx, MAG_EINVAL, "unknown workflow");
-  if (o->schedule < MAG_SCHED_AUTO || o->schedule > MAG_SCHED_PLAIN)
+  if (o->schedule < MAG_SCHED_AUTO || o->schedule > MAG_SCHED_GRAPH)
     return fail(ctx, MAG_EINVAL, "unknown schedule");
   if (!std::isnan(o->mu_fixed) && !std::isfinite(o->mu_fixed))
     return fail(ctx, MAG_EINVAL, "mu_fixed must be finite or NaN");
@@ -712,6 +770,9 @@ void mag_destroy(mag_ctx* ctx) {
   const bool own = ctx->own_stream;
   hipStream_t s = ctx->stream;
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
+  if (ctx->h_state_pinned) (void)hipHostFree(ctx->h_state_pinned);
+  if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
   delete ctx;  // DevBuf destructors free device memory
   if (own && s) (void)hipStreamDestroy(s);
 }
@@ -1076,6 +1137,7 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
   ctx->nnz = nnz;
   ctx->nblk = nblk;
   ctx->has_system = true;
+  ++ctx->sys_gen;  // captured solves of the previous system are stale
   ctx->stats.n_columns = M;
   ctx->stats.max_cluster = NORB * maxc;
   ctx->stats.sum_cluster_nnz = ctx->sum_cluster_nnz;
@@ -1119,6 +1181,176 @@ int mag_get_clusters(mag_ctx* ctx, int64_t* clus_ptr, int32_t* clus_atoms, int64
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
+// bisection launches for brackets up to 1e7 eV wide at tolerance tol (five
+// levels per launch); launches after convergence return at once
+static int mu_rounds(double tol) {
+  const int levels = (int)std::ceil(std::log2(1e7 / tol)) + 2;
+  return (levels + mu_levels_per_round() - 1) / mu_levels_per_round();
+}
+
+static int mu_grid(const mag_ctx* ctx) {
+  // two blocks per CU at most: each thread walks a few Ritz terms, and the
+  // last block's sum over the per-block partials stays short
+  return (int)std::min<int64_t>(512, std::max<int64_t>(1, (ctx->M * ctx->nu + 255) / 256));
+}
+
+// enqueue the bisection for mu and the energy sums (no host synchronisation)
+static int enqueue_mu(mag_ctx* ctx, const mag_opts* opts, bool fixed) {
+  const int64_t M = ctx->M;
+  const int nu = ctx->nu;
+  const int grid = mu_grid(ctx);
+  ALLOC(ctx->partials, sizeof(double) * 64 * (size_t)grid);
+  MuState* st = ctx->state.as<MuState>();
+  const double tol = opts->mu_tol > 0 ? opts->mu_tol : 1e-12;
+  HIPCHK(launch_mu_setup(st, opts->n_electrons, opts->kT, tol, opts->mu_fixed, fixed ? 1 : 0,
+                         ctx->stream));
+  if (!fixed) {
+    HIPCHK(launch_mu_init(ctx->eps.as<double>(), ctx->w.as<double>(), ctx->nu_eff.as<int32_t>(),
+                          M, nu, st, ctx->partials.as<double>(), grid, ctx->stream));
+    const int rounds = mu_rounds(tol);
+    for (int r = 0; r < rounds; ++r)
+      HIPCHK(launch_mu_round(ctx->eps.as<double>(), ctx->w.as<double>(),
+                             ctx->nu_eff.as<int32_t>(), M, nu, st, ctx->partials.as<double>(),
+                             grid, ctx->stream));
+  }
+  HIPCHK(launch_energy(ctx->eps.as<double>(), ctx->w.as<double>(), ctx->nu_eff.as<int32_t>(), M,
+                       nu, st, ctx->partials.as<double>(), grid, ctx->stream));
+  return MAG_OK;
+}
+
+// checks and outputs once ctx->h_state holds the final state
+static int finish_solve(mag_ctx* ctx, const mag_opts* opts, bool fixed, double* mu,
+                        double* E_band, double* A_free) {
+  ctx->stats.bisect_levels = ctx->h_state.levels;
+  if (ctx->h_state.err & KERR_NONFINITE) return fail(ctx, MAG_ENONFINITE, "non-finite Ritz data");
+  if (!fixed && !ctx->h_state.done)
+    return fail(ctx, MAG_EBRACKET, "bisection did not reach the tolerance");
+  if (!std::isfinite(ctx->h_state.E) || !std::isfinite(ctx->h_state.mu))
+    return fail(ctx, MAG_ENONFINITE, "non-finite energy");
+  ctx->solved = true;
+  if (mu) *mu = ctx->h_state.mu;
+  if (E_band) *E_band = ctx->h_state.E;
+  if (A_free) *A_free = ctx->h_state.E - opts->kT * ctx->h_state.S_ent;
+  return MAG_OK;
+}
+
+static bool same_opts(const mag_opts& a, const mag_opts& b) {
+  auto same = [](double x, double y) { return x == y || (std::isnan(x) && std::isnan(y)); };
+  return a.nu == b.nu && same(a.kT, b.kT) && same(a.n_electrons, b.n_electrons) &&
+         same(a.mu_tol, b.mu_tol) && same(a.mu_fixed, b.mu_fixed) &&
+         same(a.breakdown, b.breakdown) && a.workflow == b.workflow;
+}
+
+static bool graph_usable(const mag_ctx* ctx, const mag_opts& resolved) {
+  const auto& g = ctx->graph;
+  return g.exec && g.alloc_gen == ctx->alloc_gen && g.sys_gen == ctx->sys_gen &&
+         same_opts(g.key, resolved);
+}
+
+// Capture the forward solve just run eagerly (all buffers sized, plans tuned):
+// pass 1 over every chunk, the bisection and the energies, and the copy of
+// the final state to pinned host memory.  Host-side column lists of the
+// persistent launches are uploaded beforehand into buffers the graph owns.
+static int capture_solve(mag_ctx* ctx, ColumnJob& job, const mag_opts* opts, bool fixed) {
+  auto& g = ctx->graph;
+  if (g.exec) {
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+  }
+  job.schedule = MAG_SCHED_PERSISTENT;
+  const int64_t n = (int64_t)job.cols_host.size();
+  const int64_t bsz = chunk_columns(job, n);
+  std::vector<KrylovShapeInfo> shapes;
+  std::vector<int8_t> bucket;
+  TRY(column_buckets(ctx, job, shapes, bucket));
+  const int nbk = (int)shapes.size();
+  GraphLists gl;
+  std::vector<int32_t> all_slots;
+  std::vector<int64_t> all_qbeg;
+  for (int64_t i0 = 0; i0 < n; i0 += bsz) {
+    const int64_t cnt = std::min(bsz, n - i0);
+    std::vector<int32_t> hs;
+    std::vector<int64_t> hq, bo;
+    chunk_lists(ctx, job.cols_host.data() + i0, bucket.data() + i0, cnt, nbk, hs, hq, bo);
+    gl.slot_base.push_back((int64_t)all_slots.size());
+    gl.boff.push_back(bo);
+    all_slots.insert(all_slots.end(), hs.begin(), hs.end());
+    all_qbeg.insert(all_qbeg.end(), hq.begin(), hq.end());
+  }
+  const int64_t nchunks = (int64_t)gl.boff.size();
+  ALLOC(g.slots, sizeof(int32_t) * std::max<size_t>(1, all_slots.size()));
+  ALLOC(g.qbeg, sizeof(int64_t) * std::max<size_t>(1, all_qbeg.size()));
+  ALLOC(g.queue, sizeof(int32_t) * KRYLOV_QUEUES * nbk * nchunks);
+  HIPCHK(hipMemcpyAsync(g.slots.p, all_slots.data(), sizeof(int32_t) * all_slots.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(g.qbeg.p, all_qbeg.data(), sizeof(int64_t) * all_qbeg.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  if (!ctx->h_state_pinned) {
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, sizeof(MuState), hipHostMallocDefault));
+    ctx->h_state_pinned = static_cast<MuState*>(p);
+  }
+  TRY(sync(ctx));
+  gl.slots = g.slots.as<int32_t>();
+  gl.qbeg = g.qbeg.as<int64_t>();
+  gl.queue = g.queue.as<int32_t>();
+  const uint64_t gen_before = ctx->alloc_gen;
+
+  HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+  ctx->time_kernels = false;
+  int rc = run_columns(ctx, job, &gl);
+  if (rc == MAG_OK) rc = enqueue_mu(ctx, opts, fixed);
+  hipError_t ce = hipSuccess;
+  if (rc == MAG_OK)
+    ce = hipMemcpyAsync(ctx->h_state_pinned, ctx->state.p, sizeof(MuState),
+                        hipMemcpyDeviceToHost, ctx->stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(ctx->stream, &graph);
+  if (rc != MAG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ce != hipSuccess || ee != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return fail(ctx, MAG_EHIP, "capture of the forward solve failed");
+  }
+  const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    g.exec = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, MAG_EHIP, "instantiation of the forward solve graph failed");
+  }
+  if (ctx->alloc_gen != gen_before) {  // a buffer moved while capturing: do not keep it
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    return MAG_OK;
+  }
+  g.alloc_gen = ctx->alloc_gen;
+  g.sys_gen = ctx->sys_gen;
+  g.key = ctx->opts;
+  return MAG_OK;
+}
+
+// replay of a captured forward solve
+static int replay_solve(mag_ctx* ctx, const mag_opts* opts, bool fixed, double* mu,
+                        double* E_band, double* A_free) {
+  Timer t(ctx->stream);
+  HIPCHK(hipGraphLaunch(ctx->graph.exec, ctx->stream));
+  TRY(sync(ctx));
+  const double ms = t.stop_ms();
+  ctx->stats.t_pass1_ms = ms;
+  ctx->stats.t_krylov_ms = 0.0;
+  ctx->stats.t_eig_ms = 0.0;
+  ctx->stats.krylov_launches = 0;
+  ctx->stats.t_mu_ms = 0.0;
+  ctx->stats.schedule_used = MAG_SCHED_GRAPH;
+  TRY(take_errors(ctx, "pass 1"));
+  ctx->h_state = *ctx->h_state_pinned;
+  return finish_solve(ctx, opts, fixed, mu, E_band, A_free);
+}
+
 int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_band,
                       double* A_free) {
   TRY(ensure_system(ctx));
@@ -1146,6 +1378,8 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
   ALLOC(ctx->nu_eff, sizeof(int32_t) * M);
   const bool store = ctx->opts.workflow == MAG_WORKFLOW_STORE;
   if (store) ALLOC(ctx->P, sizeof(double) * ctx->nnz * nu);
+  if (opts->schedule == MAG_SCHED_GRAPH && graph_usable(ctx, ctx->opts))
+    return replay_solve(ctx, opts, fixed, mu, E_band, A_free);
 
   // ---- pass 1
   Timer t1(ctx->stream);
@@ -1172,50 +1406,16 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
 
   // ---- chemical potential and energies
   Timer t2(ctx->stream);
-  // two blocks per CU at most: each thread walks a few Ritz terms, and the
-  // last block's sum over the per-block partials stays short
-  const int grid = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M * nu + 255) / 256));
-  ALLOC(ctx->partials, sizeof(double) * 64 * (size_t)grid);
-  MuState h{};
-  h.ne = opts->n_electrons;
-  h.kT = opts->kT;
-  h.tol = opts->mu_tol > 0 ? opts->mu_tol : 1e-12;
-  h.counter = 0;
-  if (fixed) {
-    h.mu = opts->mu_fixed;
-    h.done = 1;
-  }
-  HIPCHK(hipMemcpyAsync(ctx->state.p, &h, sizeof(MuState), hipMemcpyHostToDevice, ctx->stream));
-  MuState* st = ctx->state.as<MuState>();
-  if (!fixed) {
-    HIPCHK(launch_mu_init(ctx->eps.as<double>(), ctx->w.as<double>(), ctx->nu_eff.as<int32_t>(),
-                          M, nu, st, ctx->partials.as<double>(), grid, ctx->stream));
-    MuState hs{};
-    HIPCHK(hipMemcpyAsync(&hs, st, sizeof(MuState), hipMemcpyDeviceToHost, ctx->stream));
-    TRY(sync(ctx));
-    if (hs.err & KERR_NONFINITE) return fail(ctx, MAG_ENONFINITE, "non-finite Ritz data");
-    const double width = hs.hi - hs.lo;
-    const int levels = width > h.tol ? (int)std::ceil(std::log2(width / h.tol)) + 2 : 1;
-    const int rounds = (levels + mu_levels_per_round() - 1) / mu_levels_per_round();
-    for (int r = 0; r < rounds; ++r)
-      HIPCHK(launch_mu_round(ctx->eps.as<double>(), ctx->w.as<double>(),
-                             ctx->nu_eff.as<int32_t>(), M, nu, st, ctx->partials.as<double>(),
-                             grid, ctx->stream));
-  }
-  HIPCHK(launch_energy(ctx->eps.as<double>(), ctx->w.as<double>(), ctx->nu_eff.as<int32_t>(), M,
-                       nu, st, ctx->partials.as<double>(), grid, ctx->stream));
-  HIPCHK(hipMemcpyAsync(&ctx->h_state, st, sizeof(MuState), hipMemcpyDeviceToHost, ctx->stream));
+  TRY(enqueue_mu(ctx, opts, fixed));
+  HIPCHK(hipMemcpyAsync(&ctx->h_state, ctx->state.p, sizeof(MuState), hipMemcpyDeviceToHost,
+                        ctx->stream));
   TRY(sync(ctx));
   ctx->stats.t_mu_ms = t2.stop_ms();
-  ctx->stats.bisect_levels = ctx->h_state.levels;
-  if (!fixed && !ctx->h_state.done)
-    return fail(ctx, MAG_EBRACKET, "bisection did not reach the tolerance");
-  if (!std::isfinite(ctx->h_state.E) || !std::isfinite(ctx->h_state.mu))
-    return fail(ctx, MAG_ENONFINITE, "non-finite energy");
-  ctx->solved = true;
-  if (mu) *mu = ctx->h_state.mu;
-  if (E_band) *E_band = ctx->h_state.E;
-  if (A_free) *A_free = ctx->h_state.E - opts->kT * ctx->h_state.S_ent;
+  TRY(finish_solve(ctx, opts, fixed, mu, E_band, A_free));
+  if (opts->schedule == MAG_SCHED_GRAPH) {
+    const int rc = capture_solve(ctx, job, opts, fixed);
+    if (rc != MAG_OK) return rc;
+  }
   return MAG_OK;
 }
 

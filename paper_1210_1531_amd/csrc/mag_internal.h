@@ -183,6 +183,8 @@ int eig_rec_cap(int cap);
 int eig_sweep_cap(int cap);
 hipError_t launch_density(const DensityArgs& a, hipStream_t s);
 
+hipError_t launch_mu_setup(MuState* st, double ne, double kT, double tol, double mu_fixed,
+                           int fixed, hipStream_t s);
 hipError_t launch_mu_init(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
                           int nu, MuState* st, double* partials, int grid, hipStream_t s);
 hipError_t launch_mu_round(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
@@ -292,6 +294,18 @@ struct mag_ctx {
   mag::DevBuf k_trid, k_evu, k_rot, k_sweep, k_qlst, k_fbl, k_fbc, k_slots;
   // Krylov launch plan per (nu capacity, workgroup shape of the bucket)
   std::map<std::pair<int, int>, mag::KrylovPlan> kplans;
+  // generations: bumped when a device buffer moves / the system changes
+  uint64_t alloc_gen = 0, sys_gen = 0;
+  // captured forward solve (schedule MAG_SCHED_GRAPH)
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    uint64_t alloc_gen = 0, sys_gen = 0;
+    mag_opts key{};
+    int rounds = 0;
+    mag::DevBuf slots, qbeg, queue;  // column lists of the captured launches
+  } graph;
+  mag::MuState* h_state_pinned = nullptr;  // read back at the end of a captured solve
+  hipStream_t aux_stream = nullptr;        // capture stream when the context's is the null stream
   mag::DevBuf tmp_cols, tmp_off, tmp_out;
   int64_t batch_cols = 0;
   mag::MuState h_state{};

@@ -328,6 +328,28 @@ __global__ __launch_bounds__(MTPB) void energy_kernel(const double* eps, const d
   }
 }
 
+// state of a solve: the inputs of the bisection, everything else cleared
+// (a kernel, so that a captured solve needs no host-to-device copy)
+__global__ void mu_setup_kernel(MuState* st, double ne, double kT, double tol, double mu_fixed,
+                                int fixed) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  MuState h{};
+  h.ne = ne;
+  h.kT = kT;
+  h.tol = tol;
+  if (fixed) {
+    h.mu = mu_fixed;
+    h.done = 1;
+  }
+  *st = h;
+}
+
+hipError_t launch_mu_setup(MuState* st, double ne, double kT, double tol, double mu_fixed,
+                           int fixed, hipStream_t s) {
+  hipLaunchKernelGGL(mu_setup_kernel, dim3(1), dim3(64), 0, s, st, ne, kT, tol, mu_fixed, fixed);
+  return hipGetLastError();
+}
+
 hipError_t launch_mu_init(const double* eps, const double* w, const int32_t* nu_eff, int64_t M,
                           int nu, MuState* st, double* partials, int grid, hipStream_t s) {
   hipLaunchKernelGGL(mu_init_kernel, dim3(grid), dim3(MTPB), 0, s, eps, w, nu_eff, M, nu, st,

@@ -28,7 +28,8 @@ class MagError(RuntimeError):
 _WORKFLOWS = {"recompute": L.MAG_WORKFLOW_RECOMPUTE, "store": L.MAG_WORKFLOW_STORE,
               "auto": L.MAG_WORKFLOW_AUTO}
 _SCHEDULES = {"auto": L.MAG_SCHED_AUTO, "persistent": L.MAG_SCHED_PERSISTENT,
-              "grid": L.MAG_SCHED_GRID, "plain": L.MAG_SCHED_PLAIN}
+              "grid": L.MAG_SCHED_GRID, "plain": L.MAG_SCHED_PLAIN,
+              "graph": L.MAG_SCHED_GRAPH}
 
 _NP = {np.float64: (torch.float64 if torch else None), np.int32: (torch.int32 if torch else None),
        np.int64: (torch.int64 if torch else None)}

@@ -103,6 +103,43 @@ def test_workflows_and_schedules_are_bitwise_equal():
             assert np.array_equal(np.asarray(a), np.asarray(b)), key
 
 
+@pytest.mark.parametrize("workflow", ["store", "recompute"])
+def test_captured_solve_replays_match_eager(workflow):
+    # schedule "graph": the first solve runs eagerly and captures the forward
+    # pass; later solves replay it.  Each replay, with eager work and host
+    # synchronisation between replays, must give the eager result bit for bit;
+    # a buffer that grows in between forces a new capture.
+    import torch
+    log(f"[graph] mini_vac {workflow}")
+    s, _ = oracle_system("mini_vac")
+    ctx = gpu_context(s)
+    opts = dict(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow=workflow)
+
+    def result():
+        eps, w, nu_eff = (np_(x) for x in ctx.spectra())
+        rho, pi = (np_(x) for x in ctx.density_matrix())
+        return eps, w, nu_eff, rho, pi
+
+    ref_scalars = ctx.solve(**opts, schedule="persistent")
+    ref = result()
+    replays = 0
+    for rep in range(5):
+        scalars = ctx.solve(**opts, schedule="graph")
+        used = ctx.stats()["schedule_used"]
+        assert used == (1 if rep == 0 else used) and used in (1, 4), (rep, used)
+        replays += used == 4
+        assert scalars == ref_scalars, rep
+        for a, b in zip(ref, result()):
+            assert np.array_equal(a, b), rep
+        x = torch.ones(1 << 20, dtype=torch.float64, device="cuda")  # unrelated eager work
+        torch.cuda.synchronize()
+        assert float(x.sum()) == float(1 << 20)
+        if rep == 1:
+            ctx.cluster_columns(np.array([0, 7], dtype=np.int32))  # grows the column scratch
+    assert replays >= 3
+    log(f"[graph] {workflow}: {replays} replays equal to the eager solve")
+
+
 def test_forces_match_oracle_and_sum_to_zero():
     log("[forces] mini_vac")
     from oracle import solve
