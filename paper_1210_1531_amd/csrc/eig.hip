@@ -26,6 +26,8 @@
 //  A column whose rotation record would overflow its fixed slots (or whose
 //  QL did not converge in the lane kernel) is finished by a fallback kernel
 //  that runs the same QL inside one wave with the rotations applied directly.
+#include <algorithm>
+
 #include "mag_internal.h"
 #include "wave.h"
 
@@ -35,7 +37,7 @@ constexpr int ETPB = 64;
 constexpr int QL_MAXIT = 60;  // QL iterations per eigenvalue before giving up
 
 int eig_rec_cap(int cap) { return 2 * cap * cap; }
-int eig_sweep_cap(int cap) { return 4 * cap; }
+int eig_sweep_cap(int cap) { return std::min(4 * cap, 128); }  // two header registers per lane
 
 // ---------------------------------------------------------------------------
 // 1. Cholesky, C = L^-1 h L^-T, Householder tridiagonalization
@@ -408,15 +410,30 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
     const int nsw = a.qlst[slot];
     const double2* rec = reinterpret_cast<const double2*>(a.rot) + slot * (int64_t)a.rec_cap;
     const int32_t* sw = a.sweep + slot * (int64_t)a.sweep_cap;
+    // every sweep header in registers (lane q holds sweeps q and q + 64), and
+    // the next sweep's rotations loaded while the current one is applied
+    const int h0 = lane < nsw ? sw[lane] : 0;
+    const int h1 = lane + 64 < nsw ? sw[lane + 64] : 0;
+    auto header = [&](int q) {
+      return q < 64 ? __builtin_amdgcn_readlane(h0, q) : __builtin_amdgcn_readlane(h1, q - 64);
+    };
+    // lane t holds the rotation of the plane (t, t+1); sweep (ms, cnt) ran t = ms-1 down to ms-cnt
+    auto fetch = [&](int hdr, int ptr) {
+      const int ms = hdr >> 8, lo = ms - (hdr & 255);
+      double2 r = make_double2(0.0, 1.0);
+      if (lane < ms && lane >= lo) r = rec[ptr + (ms - 1 - lane)];
+      return r;
+    };
+    int hdr = nsw > 0 ? header(0) : 0;
     int ptr = 0;
+    double2 next = fetch(hdr, 0);
     for (int q = 0; q < nsw; ++q) {
-      const int hdr = sw[q];
       const int ms = hdr >> 8, cnt = hdr & 255;
       const int lo = ms - cnt;
-      // lane t holds the rotation of the plane (t, t+1); the sweep ran t = ms-1 down to lo
-      double2 rt = make_double2(0.0, 1.0);
-      if (lane < ms && lane >= lo) rt = rec[ptr + (ms - 1 - lane)];
-      ptr += cnt;
+      const double2 rt = next;
+      const int ptr_n = ptr + cnt;
+      const int hdr_n = (q + 1 < nsw) ? header(q + 1) : 0;
+      if (q + 1 < nsw) next = fetch(hdr_n, ptr_n);
 #pragma unroll
       for (int i = NM - 2; i >= 0; --i) {
         if (i < ms && i >= lo) {
@@ -429,6 +446,8 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
           z[i] = fma(cs, z[i], -sn * zf);
         }
       }
+      hdr = hdr_n;
+      ptr = ptr_n;
     }
     if (lane < n) ev[lane] = a.evu[slot * (int64_t)NM + lane];
   } else {
