@@ -10,7 +10,9 @@
 //   w = H_C q_k, z = S_C q_k       one fused SpMV (shared pattern and gathers)
 //   h[:,k] = Q^T w, s[:,k] = Q^T z  projection, taken from the first
 //                                   Gram-Schmidt pass's dot products
-//   w -= Q h[:,k]; c = Q^T w; w -= Q c   classical Gram-Schmidt, twice
+//   w -= Q h[:,k]; c = Q^T w; w -= Q c   classical Gram-Schmidt; the second
+//                                        pass runs when the first one removed
+//                                        more than half of |w|^2
 //   q_{k+1} = w / |w|                    (breakdown: |w| <= tol |H q_k|)
 // The basis is Euclidean-orthonormal; it spans the same Krylov space
 // K_nu(H_C; e_l) as the S-orthonormal basis of the method's reading, so the
@@ -360,7 +362,8 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       }
       if (go) {
 
-      // ---- w -= Q h[:, k], then the second pass c = Q^T w (one sweep)
+      // ---- w -= Q h[:, k]; |h|^2 rides along (columns past k hold zeros)
+      double hsq = 0.0;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         if (c <= kc) {
@@ -369,82 +372,89 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             const int i = c * 8 + t;
             if (i < NU) {
               const double hi = s_fin[c * 16 + t];
+              hsq = fma(hi, hi, hsq);
 #pragma unroll
               for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], hi, w[rr]);
             }
           }
         }
       }
+      // second pass c = Q^T w, w -= Q c only when the first pass cancelled
+      // more than half of |w|^2 (the criterion of Daniel, Gragg, Kaufman and
+      // Stewart, eta = 1/sqrt 2); otherwise |w|^2 - |h|^2 is the new norm^2
+      double beta2 = ww1 - hsq;
+      if (!(beta2 > 0.5 * ww1)) {
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        if (c <= kc) {
-          double v[8];
+        for (int c = 0; c < NCH; ++c) {
+          if (c <= kc) {
+            double v[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int i = c * 8 + t;
-            double p = 0.0;
-            if (i < NU) {
+            for (int t = 0; t < 8; ++t) {
+              const int i = c * 8 + t;
+              double p = 0.0;
+              if (i < NU) {
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr) p = fma(qv[rr][i], w[rr], p);
+                for (int rr = 0; rr < R; ++rr) p = fma(qv[rr][i], w[rr], p);
+              }
+              v[t] = p;
             }
-            v[t] = p;
-          }
-          const double r8 = reduce8(v);
-          if ((lane & 7) == 0) {
-            const int idx = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-            s_red[wave][c * 8 + idx] = r8;
-          }
-        }
-      }
-      {
-        double ww = 0.0;
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-        ww = wave_allreduce(ww);
-        if (lane == 0) s_red[wave][8 * NCH] = ww;
-      }
-      __syncthreads();
-      {
-        const int nval = 8 * (kc + 1);
-        for (int t = tid; t <= nval; t += KTPB) {
-          const int tt = (t == nval) ? 8 * NCH : t;
-          double acc = s_red[0][tt];
-#pragma unroll
-          for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
-          s_fin[tt] = acc;
-        }
-      }
-      __syncthreads();
-      double csq = 0.0;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        if (c <= kc) {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int i = c * 8 + t;
-            if (i < NU) {
-              const double ci = s_fin[c * 8 + t];
-              csq = fma(ci, ci, csq);
-#pragma unroll
-              for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], ci, w[rr]);
+            const double r8 = reduce8(v);
+            if ((lane & 7) == 0) {
+              const int idx = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+              s_red[wave][c * 8 + idx] = r8;
             }
           }
         }
-      }
-      double beta2 = s_fin[8 * NCH] - csq;
-      if (!(beta2 > 0.5 * s_fin[8 * NCH])) {
-        // the second pass removed a large part: take the norm explicitly
-        __syncthreads();
-        double ww = 0.0;
+        {
+          double ww = 0.0;
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-        ww = wave_allreduce(ww);
-        if (lane == 0) s_red[wave][0] = ww;
+          for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
+          ww = wave_allreduce(ww);
+          if (lane == 0) s_red[wave][8 * NCH] = ww;
+        }
         __syncthreads();
-        double acc = s_red[0][0];
+        {
+          const int nval = 8 * (kc + 1);
+          for (int t = tid; t <= nval; t += KTPB) {
+            const int tt = (t == nval) ? 8 * NCH : t;
+            double acc = s_red[0][tt];
 #pragma unroll
-        for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][0];
-        beta2 = acc;
+            for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
+            s_fin[tt] = acc;
+          }
+        }
+        __syncthreads();
+        double csq = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          if (c <= kc) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int i = c * 8 + t;
+              if (i < NU) {
+                const double ci = s_fin[c * 8 + t];
+                csq = fma(ci, ci, csq);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], ci, w[rr]);
+              }
+            }
+          }
+        }
+        beta2 = s_fin[8 * NCH] - csq;
+        if (!(beta2 > 0.5 * s_fin[8 * NCH])) {
+          // the second pass removed a large part: take the norm explicitly
+          __syncthreads();
+          double ww = 0.0;
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
+          ww = wave_allreduce(ww);
+          if (lane == 0) s_red[wave][0] = ww;
+          __syncthreads();
+          double acc = s_red[0][0];
+#pragma unroll
+          for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][0];
+          beta2 = acc;
+        }
       }
       // breakdown: |w| <= tol |H q_k|, compared in squares
       const double b2 = fmax(beta2, 0.0);
