@@ -106,7 +106,8 @@ def cpu_baseline(struct, target_s):
         "unit": "columns/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"{cols.size} of {M} columns (every {step}th atom, all 4 orbitals), mode-K "
+        "sample": f"{cols.size} of {M} columns ({atoms.size} atoms: every {step}-th from atom 0, "
+                  f"all 4 orbitals), mode-K "
                   f"Ritz data + pattern rows, {wall:.1f} s wall on {cores} processes",
     }
 

@@ -96,312 +96,261 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   const int cap = a.cap;
   int q = a.queue ? (int)(blockIdx.x % (unsigned)a.nqueue) : 0;
   int tried = 0;
+  // a queue hands out the NORB columns of an atom together while more than
+  // `tail` columns remain in it, and single columns after that; the columns
+  // of one atom share the cluster tables built by the prologue
+  const int64_t tail = a.queue ? (int64_t)NORB * (gridDim.x / a.nqueue + 1) : 0;
+  int tabJ = -1;  // atom whose cluster tables the LDS holds (-1: none)
+  int tab_jl = 0, tab_ncache = 0;
 
   for (int64_t it = 0;; ++it) {
-    int64_t slot;
+    int64_t base;
+    int count;
     if (a.queue) {
       if (tid == 0) {
         int64_t sl = -1;
+        int n = 0;
         while (tried < a.nqueue) {
-          const int64_t cand = a.qbeg[q] + atomicAdd(&a.queue[q], 1);
-          if (cand < a.qbeg[q + 1]) {
+          const int64_t qb = a.qbeg[q], qe = a.qbeg[q + 1];
+          const int64_t seen = qb + atomicAdd(&a.queue[q], 0);
+          const int g = (qe - seen > tail) ? NORB : 1;
+          const int64_t cand = qb + atomicAdd(&a.queue[q], g);
+          if (cand < qe) {
             sl = cand;
+            n = (int)min((int64_t)g, qe - cand);
             break;
           }
           q = (q + 1) % a.nqueue;
           ++tried;
         }
         s_misc[0] = (int)sl;
+        s_misc[2] = n;
       }
       __syncthreads();
-      slot = s_misc[0];
+      base = s_misc[0];
+      count = s_misc[2];
       __syncthreads();
-      if (slot < 0) break;
+      if (base < 0) break;
     } else {
       if (it > 0) break;
-      slot = blockIdx.x;
+      base = blockIdx.x;
+      count = 1;
     }
-    if (slot >= a.ncols) break;
-    if (a.slots) slot = a.slots[slot];  // this launch covers a subset of the slots
+    if (base >= a.ncols) break;
 
-    const int j = a.cols[slot];
-    const int J = j >> 2;
-    const int alpha = j & 3;
-    const int64_t c0 = a.clus_ptr[J];
-    const int nat = (int)(a.clus_ptr[J + 1] - c0);
-    const int nC = NORB * nat;
-    if (nat > CLUSTER_MAX || nC > KTPB * R || nat <= 0) {
-      if (tid == 0) {
-        atomicOr(a.err, (int)KERR_CAPACITY);
-        a.nu_eff[slot] = 0;
-      }
-      continue;
-    }
+    for (int u = 0; u < count; ++u) {
+      int64_t slot = base + u;
+      if (a.slots) slot = a.slots[slot];  // this launch covers a subset of the slots
 
-    // ---- prologue: cluster atoms and local block rows (gather of H_C, S_C)
-    for (int i = tid; i < nat; i += KTPB) s_atoms[i] = a.clus_atoms[c0 + i];
-    for (int i = tid; i < nC; i += KTPB) s_pat[i] = -1;
-    __syncthreads();
-    for (int i = tid; i < nat; i += KTPB) {
-      const int I = s_atoms[i];
-      int cnt = 0;
-      for (int b = a.bptr[I]; b < a.bptr[I + 1]; ++b)
-        if (lds_find(s_atoms, nat, a.bcol[b]) >= 0) ++cnt;
-      s_lptr[i + 1] = cnt;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int acc = 0;
-      s_lptr[0] = 0;
-      for (int i = 0; i < nat; ++i) {
-        acc += s_lptr[i + 1];
-        s_lptr[i + 1] = acc;
-      }
-      s_misc[1] = lds_find(s_atoms, nat, J);
-    }
-    __syncthreads();
-    const int jl = s_misc[1];
-    const int nent = s_lptr[nat];
-    const int nbJ = a.bptr[J + 1] - a.bptr[J];
-    const int nbJl = (jl >= 0) ? s_lptr[jl + 1] - s_lptr[jl] : -1;
-    if (nent > ENT_MAX || jl < 0 || nbJl != nbJ) {
-      if (tid == 0) {
-        atomicOr(a.err, (int)(nent > ENT_MAX ? KERR_CAPACITY : KERR_PATTERN));
-        a.nu_eff[slot] = 0;
-      }
-      __syncthreads();
-      continue;
-    }
-    // cached entry e sits at e * 17 double2 (272 bytes): the 16-byte pad puts
-    // consecutive atoms of a wave on different LDS bank groups
-    const int ncache = min(nent, a.cache_cap);
-    for (int i = tid; i < nat; i += KTPB) {
-      const int I = s_atoms[i];
-      const int b0 = a.bptr[I];
-      int e = s_lptr[i];
-      for (int b = b0; b < a.bptr[I + 1]; ++b) {
-        const int kl = lds_find(s_atoms, nat, a.bcol[b]);
-        if (kl >= 0) {
-          s_ent[e] = (uint16_t)(((b - b0) << 8) | kl);
-          if (e < ncache) s_cblk[e] = b;
-          ++e;
+      const int j = a.cols[slot];
+      const int J = j >> 2;
+      const int alpha = j & 3;
+      const int64_t c0 = a.clus_ptr[J];
+      const int nat = (int)(a.clus_ptr[J + 1] - c0);
+      const int nC = NORB * nat;
+      if (nat > CLUSTER_MAX || nC > KTPB * R || nat <= 0) {
+        if (tid == 0) {
+          atomicOr(a.err, (int)KERR_CAPACITY);
+          a.nu_eff[slot] = 0;
         }
+        continue;
       }
-    }
-    __syncthreads();
-    // pattern rows of column j: block row of J, in CSR order (block t, orbital)
-    for (int t = tid; t < NORB * nbJ; t += KTPB) {
-      const int kl = (int)(s_ent[s_lptr[jl] + (t >> 2)] & 255);
-      s_pat[NORB * kl + (t & 3)] = (int16_t)t;
-    }
-    {
-      const double2* bv2 = reinterpret_cast<const double2*>(a.bval);
-      for (int idx = tid; idx < ncache * 16; idx += KTPB)
-        s_cache[(idx >> 4) * CSLOT + (idx & 15)] = bv2[(int64_t)s_cblk[idx >> 4] * 16 + (idx & 15)];
-    }
-    const int ell = NORB * jl + alpha;
-    for (int i = tid; i < nC; i += KTPB) s_x[i] = (i == ell) ? 1.0 : 0.0;
+      const int nbJ = a.bptr[J + 1] - a.bptr[J];
 
-    double qv[R][NU];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-#pragma unroll
-      for (int i = 0; i < NU; ++i) qv[rr][i] = 0.0;
-      if (R * tid + rr == ell) qv[rr][0] = 1.0;
-    }
-    // row bookkeeping of this thread: entry range, the split between cached
-    // and streamed blocks, and the row's position inside its global blocks
-    int e_beg[R], e_mid[R], e_end[R], r_off[R];
-    const double* rowp[R];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      const int r = R * tid + rr;
-      e_beg[rr] = 0;
-      e_end[rr] = 0;
-      r_off[rr] = (r & 3) * 4;
-      rowp[rr] = a.bval;
-      if (r < nC) {
-        e_beg[rr] = s_lptr[r >> 2];
-        e_end[rr] = s_lptr[(r >> 2) + 1];
-        rowp[rr] = a.bval + (int64_t)a.bptr[s_atoms[r >> 2]] * 32 + r_off[rr];
+      if (J != tabJ) {
+        // ---- prologue: cluster atoms and local block rows (gather of H_C, S_C)
+        tabJ = -1;
+        for (int i = tid; i < nat; i += KTPB) s_atoms[i] = a.clus_atoms[c0 + i];
+        for (int i = tid; i < nC; i += KTPB) s_pat[i] = -1;
+        __syncthreads();
+        for (int i = tid; i < nat; i += KTPB) {
+          const int I = s_atoms[i];
+          int cnt = 0;
+          for (int b = a.bptr[I]; b < a.bptr[I + 1]; ++b)
+            if (lds_find(s_atoms, nat, a.bcol[b]) >= 0) ++cnt;
+          s_lptr[i + 1] = cnt;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int acc = 0;
+          s_lptr[0] = 0;
+          for (int i = 0; i < nat; ++i) {
+            acc += s_lptr[i + 1];
+            s_lptr[i + 1] = acc;
+          }
+          s_misc[1] = lds_find(s_atoms, nat, J);
+        }
+        __syncthreads();
+        const int jl = s_misc[1];
+        const int nent = s_lptr[nat];
+        const int nbJl = (jl >= 0) ? s_lptr[jl + 1] - s_lptr[jl] : -1;
+        if (nent > ENT_MAX || jl < 0 || nbJl != nbJ) {
+          if (tid == 0) {
+            atomicOr(a.err, (int)(nent > ENT_MAX ? KERR_CAPACITY : KERR_PATTERN));
+            a.nu_eff[slot] = 0;
+          }
+          __syncthreads();
+          continue;
+        }
+        // cached entry e sits at e * 17 double2 (272 bytes): the 16-byte pad puts
+        // consecutive atoms of a wave on different LDS bank groups
+        const int ncache = min(nent, a.cache_cap);
+        for (int i = tid; i < nat; i += KTPB) {
+          const int I = s_atoms[i];
+          const int b0 = a.bptr[I];
+          int e = s_lptr[i];
+          for (int b = b0; b < a.bptr[I + 1]; ++b) {
+            const int kl = lds_find(s_atoms, nat, a.bcol[b]);
+            if (kl >= 0) {
+              s_ent[e] = (uint16_t)(((b - b0) << 8) | kl);
+              if (e < ncache) s_cblk[e] = b;
+              ++e;
+            }
+          }
+        }
+        __syncthreads();
+        // pattern rows of column j: block row of J, in CSR order (block t, orbital)
+        for (int t = tid; t < NORB * nbJ; t += KTPB) {
+          const int kl = (int)(s_ent[s_lptr[jl] + (t >> 2)] & 255);
+          s_pat[NORB * kl + (t & 3)] = (int16_t)t;
+        }
+        {
+          const double2* bv2 = reinterpret_cast<const double2*>(a.bval);
+          for (int idx = tid; idx < ncache * 16; idx += KTPB)
+            s_cache[(idx >> 4) * CSLOT + (idx & 15)] = bv2[(int64_t)s_cblk[idx >> 4] * 16 + (idx & 15)];
+        }
+        tabJ = J;
+        tab_jl = jl;
+        tab_ncache = ncache;
       }
-      e_mid[rr] = min(max(ncache, e_beg[rr]), e_end[rr]);
-    }
-    const int nu_max = min(a.nu, nC);
-    int nu_eff = nu_max;
-    double* hcol = a.hs + slot * (int64_t)(2 * cap * cap);
-    double* scol = hcol + cap * cap;
-    __syncthreads();
+      const int jl = tab_jl;
+      const int ncache = tab_ncache;
+      const int ell = NORB * jl + alpha;
+      for (int i = tid; i < nC; i += KTPB) s_x[i] = (i == ell) ? 1.0 : 0.0;
 
-    for (int k = 0; k < nu_max; ++k) {
-      // ---- fused SpMV: w = H_C q_k, z = S_C q_k (two blocks per iteration);
-      // cached blocks come from LDS, the rest stream from L2/HBM
-      double w[R], z[R];
+      double qv[R][NU];
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
-        double wa = 0.0, za = 0.0, wb = 0.0, zb = 0.0;
-        const int ro = r_off[rr];
-        int e = e_beg[rr];
-        const int em = e_mid[rr], e1 = e_end[rr];
-        for (; e + 1 < em; e += 2) {
-          const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
-          const double2* c1p = c0p + CSLOT;
-          const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
-          const double2 g01 = c1p[0], g23 = c1p[1], t01 = c1p[8], t23 = c1p[9];
-          const int k0 = NORB * (s_ent[e] & 255), k1 = NORB * (s_ent[e + 1] & 255);
-          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
-          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
-          const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
-          const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
-          MAG_BLOCK_FMA
-        }
-        if (e < em) {
-          const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
-          const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
-          const int k0 = NORB * (s_ent[e] & 255);
-          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
-          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
-          MAG_BLOCK_FMA1
-          ++e;
-        }
-        const double* rp = rowp[rr];
-        for (; e + 1 < e1; e += 2) {
-          const unsigned p0 = s_ent[e], p1 = s_ent[e + 1];
-          const double* b0 = rp + (p0 >> 8) * 32;
-          const double* b1 = rp + (p1 >> 8) * 32;
-          const double2 h01 = *reinterpret_cast<const double2*>(b0);
-          const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
-          const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
-          const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
-          const double2 g01 = *reinterpret_cast<const double2*>(b1);
-          const double2 g23 = *reinterpret_cast<const double2*>(b1 + 2);
-          const double2 t01 = *reinterpret_cast<const double2*>(b1 + 16);
-          const double2 t23 = *reinterpret_cast<const double2*>(b1 + 18);
-          const int k0 = NORB * (p0 & 255), k1 = NORB * (p1 & 255);
-          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
-          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
-          const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
-          const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
-          MAG_BLOCK_FMA
-        }
-        if (e < e1) {
-          const unsigned p0 = s_ent[e];
-          const double* b0 = rp + (p0 >> 8) * 32;
-          const double2 h01 = *reinterpret_cast<const double2*>(b0);
-          const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
-          const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
-          const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
-          const int k0 = NORB * (p0 & 255);
-          const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
-          const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
-          MAG_BLOCK_FMA1
-        }
-        w[rr] = wa + wb;
-        z[rr] = za + zb;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) qv[rr][i] = 0.0;
+        if (R * tid + rr == ell) qv[rr][0] = 1.0;
       }
-
-      // ---- first Gram-Schmidt pass dot products = projection column k
-      const int kc = k >> 3;
+      // row bookkeeping of this thread: entry range, the split between cached
+      // and streamed blocks, and the row's position inside its global blocks
+      int e_beg[R], e_mid[R], e_end[R], r_off[R];
+      const double* rowp[R];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        if (c <= kc) {
-          double v[16];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int i = c * 8 + t;
-            double ph = 0.0, ps = 0.0;
-            if (i < NU) {
-#pragma unroll
-              for (int rr = 0; rr < R; ++rr) {
-                ph = fma(qv[rr][i], w[rr], ph);
-                ps = fma(qv[rr][i], z[rr], ps);
-              }
-            }
-            v[t] = ph;
-            v[8 + t] = ps;
-          }
-          const double r16 = reduce16(v);
-          if ((lane & 3) == 0) {
-            const int idx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 +
-                            ((lane >> 2) & 1) * 2 + ((lane >> 3) & 1);
-            s_red[wave][c * 16 + idx] = r16;
-          }
+      for (int rr = 0; rr < R; ++rr) {
+        const int r = R * tid + rr;
+        e_beg[rr] = 0;
+        e_end[rr] = 0;
+        r_off[rr] = (r & 3) * 4;
+        rowp[rr] = a.bval;
+        if (r < nC) {
+          e_beg[rr] = s_lptr[r >> 2];
+          e_end[rr] = s_lptr[(r >> 2) + 1];
+          rowp[rr] = a.bval + (int64_t)a.bptr[s_atoms[r >> 2]] * 32 + r_off[rr];
         }
+        e_mid[rr] = min(max(ncache, e_beg[rr]), e_end[rr]);
       }
-      {
-        double ww = 0.0;
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-        ww = wave_allreduce(ww);
-        if (lane == 0) s_red[wave][16 * NCH] = ww;
-      }
+      const int nu_max = min(a.nu, nC);
+      int nu_eff = nu_max;
+      double* hcol = a.hs + slot * (int64_t)(2 * cap * cap);
+      double* scol = hcol + cap * cap;
       __syncthreads();
-      {
-        const int nval = 16 * (kc + 1);
-        for (int t = tid; t <= nval; t += KTPB) {
-          const int tt = (t == nval) ? 16 * NCH : t;
-          double acc = s_red[0][tt];
-#pragma unroll
-          for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
-          s_fin[tt] = acc;
-        }
-      }
-      __syncthreads();
-      const double ww1 = s_fin[16 * NCH];
-      for (int i = tid; i <= k; i += KTPB) {
-        hcol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + (i & 7)];
-        scol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + 8 + (i & 7)];
-      }
-      // a single exit at the bottom of the step keeps the basis registers in
-      // place (each early exit would need its own copy of them)
-      bool go = (k + 1 < nu_max);
-      if (!isfinite(ww1)) {
-        if (tid == 0) atomicOr(a.err, (int)KERR_NONFINITE);
-        nu_eff = k + 1;
-        go = false;
-      }
-      if (go) {
 
-      // ---- w -= Q h[:, k]; |h|^2 rides along (columns past k hold zeros)
-      double hsq = 0.0;
+      for (int k = 0; k < nu_max; ++k) {
+        // ---- fused SpMV: w = H_C q_k, z = S_C q_k (two blocks per iteration);
+        // cached blocks come from LDS, the rest stream from L2/HBM
+        double w[R], z[R];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        if (c <= kc) {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int i = c * 8 + t;
-            if (i < NU) {
-              const double hi = s_fin[c * 16 + t];
-              hsq = fma(hi, hi, hsq);
-#pragma unroll
-              for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], hi, w[rr]);
-            }
+        for (int rr = 0; rr < R; ++rr) {
+          double wa = 0.0, za = 0.0, wb = 0.0, zb = 0.0;
+          const int ro = r_off[rr];
+          int e = e_beg[rr];
+          const int em = e_mid[rr], e1 = e_end[rr];
+          for (; e + 1 < em; e += 2) {
+            const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
+            const double2* c1p = c0p + CSLOT;
+            const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
+            const double2 g01 = c1p[0], g23 = c1p[1], t01 = c1p[8], t23 = c1p[9];
+            const int k0 = NORB * (s_ent[e] & 255), k1 = NORB * (s_ent[e + 1] & 255);
+            const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+            const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+            const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
+            const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
+            MAG_BLOCK_FMA
           }
+          if (e < em) {
+            const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
+            const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
+            const int k0 = NORB * (s_ent[e] & 255);
+            const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+            const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+            MAG_BLOCK_FMA1
+            ++e;
+          }
+          const double* rp = rowp[rr];
+          for (; e + 1 < e1; e += 2) {
+            const unsigned p0 = s_ent[e], p1 = s_ent[e + 1];
+            const double* b0 = rp + (p0 >> 8) * 32;
+            const double* b1 = rp + (p1 >> 8) * 32;
+            const double2 h01 = *reinterpret_cast<const double2*>(b0);
+            const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
+            const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
+            const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
+            const double2 g01 = *reinterpret_cast<const double2*>(b1);
+            const double2 g23 = *reinterpret_cast<const double2*>(b1 + 2);
+            const double2 t01 = *reinterpret_cast<const double2*>(b1 + 16);
+            const double2 t23 = *reinterpret_cast<const double2*>(b1 + 18);
+            const int k0 = NORB * (p0 & 255), k1 = NORB * (p1 & 255);
+            const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+            const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+            const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
+            const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
+            MAG_BLOCK_FMA
+          }
+          if (e < e1) {
+            const unsigned p0 = s_ent[e];
+            const double* b0 = rp + (p0 >> 8) * 32;
+            const double2 h01 = *reinterpret_cast<const double2*>(b0);
+            const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
+            const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
+            const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
+            const int k0 = NORB * (p0 & 255);
+            const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
+            const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
+            MAG_BLOCK_FMA1
+          }
+          w[rr] = wa + wb;
+          z[rr] = za + zb;
         }
-      }
-      // second pass c = Q^T w, w -= Q c only when the first pass cancelled
-      // more than half of |w|^2 (the criterion of Daniel, Gragg, Kaufman and
-      // Stewart, eta = 1/sqrt 2); otherwise |w|^2 - |h|^2 is the new norm^2
-      double beta2 = ww1 - hsq;
-      if (!(beta2 > 0.5 * ww1)) {
+
+        // ---- first Gram-Schmidt pass dot products = projection column k
+        const int kc = k >> 3;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           if (c <= kc) {
-            double v[8];
+            double v[16];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
               const int i = c * 8 + t;
-              double p = 0.0;
+              double ph = 0.0, ps = 0.0;
               if (i < NU) {
 #pragma unroll
-                for (int rr = 0; rr < R; ++rr) p = fma(qv[rr][i], w[rr], p);
+                for (int rr = 0; rr < R; ++rr) {
+                  ph = fma(qv[rr][i], w[rr], ph);
+                  ps = fma(qv[rr][i], z[rr], ps);
+                }
               }
-              v[t] = p;
+              v[t] = ph;
+              v[8 + t] = ps;
             }
-            const double r8 = reduce8(v);
-            if ((lane & 7) == 0) {
-              const int idx = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-              s_red[wave][c * 8 + idx] = r8;
+            const double r16 = reduce16(v);
+            if ((lane & 3) == 0) {
+              const int idx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 +
+                              ((lane >> 2) & 1) * 2 + ((lane >> 3) & 1);
+              s_red[wave][c * 16 + idx] = r16;
             }
           }
         }
@@ -410,13 +359,13 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
 #pragma unroll
           for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
           ww = wave_allreduce(ww);
-          if (lane == 0) s_red[wave][8 * NCH] = ww;
+          if (lane == 0) s_red[wave][16 * NCH] = ww;
         }
         __syncthreads();
         {
-          const int nval = 8 * (kc + 1);
+          const int nval = 16 * (kc + 1);
           for (int t = tid; t <= nval; t += KTPB) {
-            const int tt = (t == nval) ? 8 * NCH : t;
+            const int tt = (t == nval) ? 16 * NCH : t;
             double acc = s_red[0][tt];
 #pragma unroll
             for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
@@ -424,7 +373,23 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           }
         }
         __syncthreads();
-        double csq = 0.0;
+        const double ww1 = s_fin[16 * NCH];
+        for (int i = tid; i <= k; i += KTPB) {
+          hcol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + (i & 7)];
+          scol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + 8 + (i & 7)];
+        }
+        // a single exit at the bottom of the step keeps the basis registers in
+        // place (each early exit would need its own copy of them)
+        bool go = (k + 1 < nu_max);
+        if (!isfinite(ww1)) {
+          if (tid == 0) atomicOr(a.err, (int)KERR_NONFINITE);
+          nu_eff = k + 1;
+          go = false;
+        }
+        if (go) {
+
+        // ---- w -= Q h[:, k]; |h|^2 rides along (columns past k hold zeros)
+        double hsq = 0.0;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           if (c <= kc) {
@@ -432,87 +397,149 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             for (int t = 0; t < 8; ++t) {
               const int i = c * 8 + t;
               if (i < NU) {
-                const double ci = s_fin[c * 8 + t];
-                csq = fma(ci, ci, csq);
+                const double hi = s_fin[c * 16 + t];
+                hsq = fma(hi, hi, hsq);
 #pragma unroll
-                for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], ci, w[rr]);
+                for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], hi, w[rr]);
               }
             }
           }
         }
-        beta2 = s_fin[8 * NCH] - csq;
-        if (!(beta2 > 0.5 * s_fin[8 * NCH])) {
-          // the second pass removed a large part: take the norm explicitly
+        // second pass c = Q^T w, w -= Q c only when the first pass cancelled
+        // more than half of |w|^2 (the criterion of Daniel, Gragg, Kaufman and
+        // Stewart, eta = 1/sqrt 2); otherwise |w|^2 - |h|^2 is the new norm^2
+        double beta2 = ww1 - hsq;
+        if (!(beta2 > 0.5 * ww1)) {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            if (c <= kc) {
+              double v[8];
+#pragma unroll
+              for (int t = 0; t < 8; ++t) {
+                const int i = c * 8 + t;
+                double p = 0.0;
+                if (i < NU) {
+#pragma unroll
+                  for (int rr = 0; rr < R; ++rr) p = fma(qv[rr][i], w[rr], p);
+                }
+                v[t] = p;
+              }
+              const double r8 = reduce8(v);
+              if ((lane & 7) == 0) {
+                const int idx = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+                s_red[wave][c * 8 + idx] = r8;
+              }
+            }
+          }
+          {
+            double ww = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
+            ww = wave_allreduce(ww);
+            if (lane == 0) s_red[wave][8 * NCH] = ww;
+          }
           __syncthreads();
-          double ww = 0.0;
+          {
+            const int nval = 8 * (kc + 1);
+            for (int t = tid; t <= nval; t += KTPB) {
+              const int tt = (t == nval) ? 8 * NCH : t;
+              double acc = s_red[0][tt];
 #pragma unroll
-          for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
-          ww = wave_allreduce(ww);
-          if (lane == 0) s_red[wave][0] = ww;
+              for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][tt];
+              s_fin[tt] = acc;
+            }
+          }
           __syncthreads();
-          double acc = s_red[0][0];
+          double csq = 0.0;
 #pragma unroll
-          for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][0];
-          beta2 = acc;
-        }
-      }
-      // breakdown: |w| <= tol |H q_k|, compared in squares
-      const double b2 = fmax(beta2, 0.0);
-      if (!(b2 > a.breakdown * a.breakdown * ww1)) {
-        nu_eff = k + 1;
-        go = false;
-      } else {
-        const double inv = rsqrt(b2);
+          for (int c = 0; c < NCH; ++c) {
+            if (c <= kc) {
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
-        // q_{k+1} into its register column.  k is uniform, so each test is a
-        // scalar branch; testing bits of a mask keeps the compiler from turning
-        // the chain into a switch whose merge copies every column
-        const unsigned long long sel = 1ull << (k + 1);
+              for (int t = 0; t < 8; ++t) {
+                const int i = c * 8 + t;
+                if (i < NU) {
+                  const double ci = s_fin[c * 8 + t];
+                  csq = fma(ci, ci, csq);
 #pragma unroll
-        for (int i = 1; i < NU; ++i) {
-          if (sel & (1ull << i)) {
-            __asm__ volatile("");  // keep the branch (no speculation into selects)
+                  for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], ci, w[rr]);
+                }
+              }
+            }
+          }
+          beta2 = s_fin[8 * NCH] - csq;
+          if (!(beta2 > 0.5 * s_fin[8 * NCH])) {
+            // the second pass removed a large part: take the norm explicitly
+            __syncthreads();
+            double ww = 0.0;
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) qv[rr][i] = w[rr];
+            for (int rr = 0; rr < R; ++rr) ww = fma(w[rr], w[rr], ww);
+            ww = wave_allreduce(ww);
+            if (lane == 0) s_red[wave][0] = ww;
+            __syncthreads();
+            double acc = s_red[0][0];
+#pragma unroll
+            for (int wv = 1; wv < KWAVES; ++wv) acc += s_red[wv][0];
+            beta2 = acc;
           }
         }
+        // breakdown: |w| <= tol |H q_k|, compared in squares
+        const double b2 = fmax(beta2, 0.0);
+        if (!(b2 > a.breakdown * a.breakdown * ww1)) {
+          nu_eff = k + 1;
+          go = false;
+        } else {
+          const double inv = rsqrt(b2);
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-          const int r = R * tid + rr;
-          if (r < nC) s_x[r] = w[rr];
+          for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
+          // q_{k+1} into its register column.  k is uniform, so each test is a
+          // scalar branch; testing bits of a mask keeps the compiler from turning
+          // the chain into a switch whose merge copies every column
+          const unsigned long long sel = 1ull << (k + 1);
+#pragma unroll
+          for (int i = 1; i < NU; ++i) {
+            if (sel & (1ull << i)) {
+              __asm__ volatile("");  // keep the branch (no speculation into selects)
+#pragma unroll
+              for (int rr = 0; rr < R; ++rr) qv[rr][i] = w[rr];
+            }
+          }
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) {
+            const int r = R * tid + rr;
+            if (r < nC) s_x[r] = w[rr];
+          }
         }
+        }
+        __syncthreads();
+        if (!go) break;
       }
+
+      // ---- epilogue: nu_eff, row l of Q, and the pattern (or all) rows of Q
+      if (tid == 0) {
+        a.nu_eff[slot] = nu_eff;
+        if (a.npat) a.npat[slot] = a.full ? nC : NORB * nbJ;
+      }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int r = R * tid + rr;
+        if (r < nC) {
+          if (r == ell) {
+            double* u = a.urow + slot * (int64_t)cap;
+#pragma unroll
+            for (int i = 0; i < NU; ++i) u[i] = qv[rr][i];
+            for (int i = NU; i < cap; ++i) u[i] = 0.0;
+          }
+          const int p = a.full ? r : (int)s_pat[r];
+          if (p >= 0) {
+            double* dst = a.qpat + (slot * (int64_t)a.pat_stride + p) * cap;
+#pragma unroll
+            for (int i = 0; i < NU; ++i) dst[i] = qv[rr][i];
+            for (int i = NU; i < cap; ++i) dst[i] = 0.0;
+          }
+        }
       }
       __syncthreads();
-      if (!go) break;
     }
-
-    // ---- epilogue: nu_eff, row l of Q, and the pattern (or all) rows of Q
-    if (tid == 0) {
-      a.nu_eff[slot] = nu_eff;
-      if (a.npat) a.npat[slot] = a.full ? nC : NORB * nbJ;
-    }
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      const int r = R * tid + rr;
-      if (r < nC) {
-        if (r == ell) {
-          double* u = a.urow + slot * (int64_t)cap;
-#pragma unroll
-          for (int i = 0; i < NU; ++i) u[i] = qv[rr][i];
-          for (int i = NU; i < cap; ++i) u[i] = 0.0;
-        }
-        const int p = a.full ? r : (int)s_pat[r];
-        if (p >= 0) {
-          double* dst = a.qpat + (slot * (int64_t)a.pat_stride + p) * cap;
-#pragma unroll
-          for (int i = 0; i < NU; ++i) dst[i] = qv[rr][i];
-          for (int i = NU; i < cap; ++i) dst[i] = 0.0;
-        }
-      }
-    }
-    __syncthreads();
   }
 }
 
