@@ -71,6 +71,18 @@ __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   zb = fma(t23.x, y23.x, zb);          \
   zb = fma(t23.y, y23.y, zb);
 
+// the same for named operands: accumulators (wacc, zacc), the block's H and S
+// rows, and x of the block column
+#define MAG_ROW_FMA(wacc, zacc, h01, h23, s01, s23, x01, x23) \
+  wacc = fma(h01.x, x01.x, wacc);                           \
+  wacc = fma(h01.y, x01.y, wacc);                           \
+  wacc = fma(h23.x, x23.x, wacc);                           \
+  wacc = fma(h23.y, x23.y, wacc);                           \
+  zacc = fma(s01.x, x01.x, zacc);                           \
+  zacc = fma(s01.y, x01.y, zacc);                           \
+  zacc = fma(s23.x, x23.x, zacc);                           \
+  zacc = fma(s23.y, x23.y, zacc);
+
 template <int NU, int R, int KTPB>
 __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   constexpr int KWAVES = KTPB / 64;
@@ -290,27 +302,33 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             MAG_BLOCK_FMA1
             ++e;
           }
+          // streamed blocks, three per iteration (twelve loads in flight)
           const double* rp = rowp[rr];
-          for (; e + 1 < e1; e += 2) {
-            const unsigned p0 = s_ent[e], p1 = s_ent[e + 1];
-            const double* b0 = rp + (p0 >> 8) * 32;
-            const double* b1 = rp + (p1 >> 8) * 32;
-            const double2 h01 = *reinterpret_cast<const double2*>(b0);
-            const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
-            const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
-            const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
-            const double2 g01 = *reinterpret_cast<const double2*>(b1);
-            const double2 g23 = *reinterpret_cast<const double2*>(b1 + 2);
-            const double2 t01 = *reinterpret_cast<const double2*>(b1 + 16);
-            const double2 t23 = *reinterpret_cast<const double2*>(b1 + 18);
-            const int k0 = NORB * (p0 & 255), k1 = NORB * (p1 & 255);
-            const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
-            const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
-            const double2 y01 = *reinterpret_cast<const double2*>(s_x + k1);
-            const double2 y23 = *reinterpret_cast<const double2*>(s_x + k1 + 2);
-            MAG_BLOCK_FMA
+          for (; e + 2 < e1; e += 3) {
+            double2 h01[3], h23[3], s01[3], s23[3];
+            int kk[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+              const unsigned p = s_ent[e + u];
+              const double* b = rp + (p >> 8) * 32;
+              h01[u] = *reinterpret_cast<const double2*>(b);
+              h23[u] = *reinterpret_cast<const double2*>(b + 2);
+              s01[u] = *reinterpret_cast<const double2*>(b + 16);
+              s23[u] = *reinterpret_cast<const double2*>(b + 18);
+              kk[u] = NORB * (int)(p & 255);
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+              const double2 x01 = *reinterpret_cast<const double2*>(s_x + kk[u]);
+              const double2 x23 = *reinterpret_cast<const double2*>(s_x + kk[u] + 2);
+              if (u == 1) {
+                MAG_ROW_FMA(wb, zb, h01[u], h23[u], s01[u], s23[u], x01, x23)
+              } else {
+                MAG_ROW_FMA(wa, za, h01[u], h23[u], s01[u], s23[u], x01, x23)
+              }
+            }
           }
-          if (e < e1) {
+          for (; e < e1; ++e) {
             const unsigned p0 = s_ent[e];
             const double* b0 = rp + (p0 >> 8) * 32;
             const double2 h01 = *reinterpret_cast<const double2*>(b0);
@@ -320,7 +338,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             const int k0 = NORB * (p0 & 255);
             const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
             const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
-            MAG_BLOCK_FMA1
+            MAG_ROW_FMA(wa, za, h01, h23, s01, s23, x01, x23)
           }
           w[rr] = wa + wb;
           z[rr] = za + zb;
