@@ -41,7 +41,7 @@ def parse(argv=None):
     ap.add_argument("--workflow", default="auto")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-column-launch baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 512 MiB fill and device copy (HBM counter calibration)")
     return ap.parse_args(argv)
