@@ -37,6 +37,31 @@ constexpr int ENT_MAX = CLUSTER_MAX * 24;  // local blocks of a cluster
 constexpr int CACHE_MAX = 640;             // cluster blocks held in LDS at most
 constexpr int CSLOT = CSLOT_BYTES / 16;    // double2 per cached block (16 + bank pad)
 
+// exclusive prefix sum of one int per thread over the workgroup (s_scan: one
+// int per wave plus one); returns the thread's offset, *total the sum
+template <int KTPB>
+__device__ __forceinline__ int block_excl_scan(int v, int32_t* s_scan, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) s_scan[wave] = inc;
+  __syncthreads();
+  int base = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < KTPB / 64; ++w) {
+    const int t = s_scan[w];
+    if (w < wave) base += t;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return base + inc - v;
+}
+
 __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   int lo = 0, hi = n - 1;
   while (lo <= hi) {
@@ -90,6 +115,9 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   constexpr int RED = 16 * NCH + 8;
   __shared__ int32_t s_atoms[CLUSTER_MAX];
   __shared__ int32_t s_lptr[CLUSTER_MAX + 1];
+  __shared__ int32_t s_brow[CLUSTER_MAX];      // first global block of each cluster atom's row
+  __shared__ int32_t s_gofs[CLUSTER_MAX + 1];  // offsets of those rows in the flattened list
+  __shared__ int32_t s_scan[KTPB / 64 + 1];
   // local block-CSR entry: (block offset in the global block row << 8) | local column atom
   __shared__ uint16_t s_ent[ENT_MAX];
   __shared__ int32_t s_cblk[CACHE_MAX];  // global block of each cached entry
@@ -170,31 +198,72 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
       const int nbJ = a.bptr[J + 1] - a.bptr[J];
 
       if (J != tabJ) {
-        // ---- prologue: cluster atoms and local block rows (gather of H_C, S_C)
+        // ---- prologue: cluster atoms and local block rows (gather of H_C, S_C).
+        // The global block rows of the cluster atoms are flattened into one
+        // list; each thread tests a contiguous chunk of it for cluster
+        // membership (binary search in the sorted atoms), and a workgroup scan
+        // of the kept counts places the local entries in CSR order.
         tabJ = -1;
-        for (int i = tid; i < nat; i += KTPB) s_atoms[i] = a.clus_atoms[c0 + i];
-        for (int i = tid; i < nC; i += KTPB) s_pat[i] = -1;
-        __syncthreads();
+        int rlen = 0;
         for (int i = tid; i < nat; i += KTPB) {
-          const int I = s_atoms[i];
-          int cnt = 0;
-          for (int b = a.bptr[I]; b < a.bptr[I + 1]; ++b)
-            if (lds_find(s_atoms, nat, a.bcol[b]) >= 0) ++cnt;
-          s_lptr[i + 1] = cnt;
+          const int I = a.clus_atoms[c0 + i];
+          const int b0 = a.bptr[I];
+          s_atoms[i] = I;
+          s_brow[i] = b0;
+          rlen = a.bptr[I + 1] - b0;
         }
+        for (int i = tid; i < nC; i += KTPB) s_pat[i] = -1;
+        int nflat = 0;
+        const int gofs = block_excl_scan<KTPB>(tid < nat ? rlen : 0, s_scan, &nflat);
+        if (tid < nat) s_gofs[tid] = gofs;
+        if (tid == 0) s_gofs[nat] = nflat;
         __syncthreads();
-        if (tid == 0) {
-          int acc = 0;
-          s_lptr[0] = 0;
-          for (int i = 0; i < nat; ++i) {
-            acc += s_lptr[i + 1];
-            s_lptr[i + 1] = acc;
+        const int chunk = (nflat + KTPB - 1) / KTPB;
+        const int f0 = min(tid * chunk, nflat), f1 = min(f0 + chunk, nflat);
+        // atom of the chunk's first flat entry
+        int ia = 0;
+        if (f0 < f1) {
+          int lo = 0, hi = nat - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_gofs[mid] <= f0) lo = mid;
+            else hi = mid - 1;
           }
+          ia = lo;
+        }
+        int kept = 0;
+        {
+          int i = ia;
+          for (int f = f0; f < f1; ++f) {
+            while (f >= s_gofs[i + 1]) ++i;
+            const int b = s_brow[i] + (f - s_gofs[i]);
+            if (lds_find(s_atoms, nat, a.bcol[b]) >= 0) ++kept;
+          }
+        }
+        int nent = 0;
+        int e = block_excl_scan<KTPB>(kept, s_scan, &nent);
+        if (tid == 0) {
+          s_lptr[nat] = nent;
           s_misc[1] = lds_find(s_atoms, nat, J);
+        }
+        const int ncache = min(nent, a.cache_cap);
+        if (nent <= ENT_MAX) {
+          int i = ia;
+          for (int f = f0; f < f1; ++f) {
+            while (f >= s_gofs[i + 1]) ++i;
+            const int off = f - s_gofs[i];
+            if (off == 0) s_lptr[i] = e;  // first flat entry of atom i's row
+            const int b = s_brow[i] + off;
+            const int kl = lds_find(s_atoms, nat, a.bcol[b]);
+            if (kl >= 0) {
+              s_ent[e] = (uint16_t)((off << 8) | kl);
+              if (e < ncache) s_cblk[e] = b;
+              ++e;
+            }
+          }
         }
         __syncthreads();
         const int jl = s_misc[1];
-        const int nent = s_lptr[nat];
         const int nbJl = (jl >= 0) ? s_lptr[jl + 1] - s_lptr[jl] : -1;
         if (nent > ENT_MAX || jl < 0 || nbJl != nbJ) {
           if (tid == 0) {
@@ -204,28 +273,13 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           __syncthreads();
           continue;
         }
-        // cached entry e sits at e * 17 double2 (272 bytes): the 16-byte pad puts
-        // consecutive atoms of a wave on different LDS bank groups
-        const int ncache = min(nent, a.cache_cap);
-        for (int i = tid; i < nat; i += KTPB) {
-          const int I = s_atoms[i];
-          const int b0 = a.bptr[I];
-          int e = s_lptr[i];
-          for (int b = b0; b < a.bptr[I + 1]; ++b) {
-            const int kl = lds_find(s_atoms, nat, a.bcol[b]);
-            if (kl >= 0) {
-              s_ent[e] = (uint16_t)(((b - b0) << 8) | kl);
-              if (e < ncache) s_cblk[e] = b;
-              ++e;
-            }
-          }
-        }
-        __syncthreads();
         // pattern rows of column j: block row of J, in CSR order (block t, orbital)
         for (int t = tid; t < NORB * nbJ; t += KTPB) {
           const int kl = (int)(s_ent[s_lptr[jl] + (t >> 2)] & 255);
           s_pat[NORB * kl + (t & 3)] = (int16_t)t;
         }
+        // cached entry e sits at e * 17 double2 (272 bytes): the 16-byte pad puts
+        // consecutive atoms of a wave on different LDS bank groups
         {
           const double2* bv2 = reinterpret_cast<const double2*>(a.bval);
           for (int idx = tid; idx < ncache * 16; idx += KTPB)
