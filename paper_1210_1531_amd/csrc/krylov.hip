@@ -310,7 +310,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         const int r = R * tid + rr;
         e_beg[rr] = 0;
         e_end[rr] = 0;
-        r_off[rr] = (r & 3) * 4;
+        r_off[rr] = (r & 3) * 2;  // row a of a block: doubles 2a, 2a+1 of each 8-double quarter
         rowp[rr] = a.bval;
         if (r < nC) {
           e_beg[rr] = s_lptr[r >> 2];
@@ -338,8 +338,8 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           for (; e + 1 < em; e += 2) {
             const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
             const double2* c1p = c0p + CSLOT;
-            const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
-            const double2 g01 = c1p[0], g23 = c1p[1], t01 = c1p[8], t23 = c1p[9];
+            const double2 h01 = c0p[0], h23 = c0p[4], s01 = c0p[8], s23 = c0p[12];
+            const double2 g01 = c1p[0], g23 = c1p[4], t01 = c1p[8], t23 = c1p[12];
             const int k0 = NORB * (s_ent[e] & 255), k1 = NORB * (s_ent[e + 1] & 255);
             const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
             const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           }
           if (e < em) {
             const double2* c0p = s_cache + e * CSLOT + (ro >> 1);
-            const double2 h01 = c0p[0], h23 = c0p[1], s01 = c0p[8], s23 = c0p[9];
+            const double2 h01 = c0p[0], h23 = c0p[4], s01 = c0p[8], s23 = c0p[12];
             const int k0 = NORB * (s_ent[e] & 255);
             const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
             const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
@@ -366,9 +366,9 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
               const unsigned p = s_ent[e + u];
               const double* b = rp + (p >> 8) * 32;
               h01[u] = *reinterpret_cast<const double2*>(b);
-              h23[u] = *reinterpret_cast<const double2*>(b + 2);
+              h23[u] = *reinterpret_cast<const double2*>(b + 8);
               s01[u] = *reinterpret_cast<const double2*>(b + 16);
-              s23[u] = *reinterpret_cast<const double2*>(b + 18);
+              s23[u] = *reinterpret_cast<const double2*>(b + 24);
               kk[u] = NORB * (int)(p & 255);
             }
 #pragma unroll
@@ -386,9 +386,9 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             const unsigned p0 = s_ent[e];
             const double* b0 = rp + (p0 >> 8) * 32;
             const double2 h01 = *reinterpret_cast<const double2*>(b0);
-            const double2 h23 = *reinterpret_cast<const double2*>(b0 + 2);
+            const double2 h23 = *reinterpret_cast<const double2*>(b0 + 8);
             const double2 s01 = *reinterpret_cast<const double2*>(b0 + 16);
-            const double2 s23 = *reinterpret_cast<const double2*>(b0 + 18);
+            const double2 s23 = *reinterpret_cast<const double2*>(b0 + 24);
             const int k0 = NORB * (p0 & 255);
             const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
             const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);

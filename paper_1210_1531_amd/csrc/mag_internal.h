@@ -80,7 +80,7 @@ struct MuState {
 struct KrylovArgs {
   const int32_t* bptr;     // N + 1 block-row pointers
   const int32_t* bcol;     // block column atom ids
-  const double* bval;      // nblk x 32: H block (row major) then S block
+  const double* bval;      // nblk x 32: H block then S block, each as quarters (columns 0-1, 2-3) of row pairs
   const int64_t* clus_ptr; // N + 1
   const int32_t* clus_atoms;
   const int32_t* cols;     // columns of this launch, in slot order

@@ -43,11 +43,15 @@ __global__ void to_blocks_kernel(const int64_t* rowptr, const double* H, const d
   const int nb = bptr[J + 1] - bptr[J];
   for (int t = 0; t < nb; ++t) {
     double* dst = bval + (int64_t)(bptr[J] + t) * 32;
+    // quarters of 8 doubles: H columns 0-1, H columns 2-3, S columns 0-1,
+    // S columns 2-3, each holding rows 0..3 as pairs; the four threads of an
+    // atom row read one contiguous 64-byte run per 16-byte load
     for (int a = 0; a < NORB; ++a) {
       const int64_t ra = rowptr[NORB * J + a] + 4 * t;
       for (int be = 0; be < NORB; ++be) {
-        dst[4 * a + be] = H[ra + be];
-        dst[16 + 4 * a + be] = S[ra + be];
+        const int o = (be >> 1) * 8 + 2 * a + (be & 1);
+        dst[o] = H[ra + be];
+        dst[16 + o] = S[ra + be];
       }
     }
   }
