@@ -525,15 +525,25 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
     const int np = a.npat[slot];
     const int64_t base = a.pmode ? a.rowptr[j] : slot * (int64_t)a.pat_stride;
     const double* qp = a.qpat + slot * (int64_t)a.pat_stride * NM;
-    for (int p = 0; p < np; ++p) {
-      const double* qrow = qp + (int64_t)p * NM;
-      double y0 = 0.0, y1 = 0.0;
+    // the pattern rows of Q are staged in LDS (over Z and L, free now) in
+    // chunks, with one coalesced copy per chunk, and read back as broadcasts
+    constexpr int PCH = (2 * NM * LD) / NM;
+    double* qs = T;
+    for (int p0 = 0; p0 < np; p0 += PCH) {
+      const int pc = min(PCH, np - p0);
+      __syncthreads();
+      for (int idx = lane; idx < pc * NM; idx += ETPB) qs[idx] = qp[(int64_t)p0 * NM + idx];
+      __syncthreads();
+      for (int p = 0; p < pc; ++p) {
+        const double* qrow = qs + p * NM;
+        double y0 = 0.0, y1 = 0.0;
 #pragma unroll
-      for (int t = 0; t < NM; t += 2) {
-        y0 = fma(qrow[t], y[t], y0);
-        if (t + 1 < NM) y1 = fma(qrow[t + 1], y[t + 1], y1);
+        for (int t = 0; t < NM; t += 2) {
+          y0 = fma(qrow[t], y[t], y0);
+          if (t + 1 < NM) y1 = fma(qrow[t + 1], y[t + 1], y1);
+        }
+        if (lane < nuo) a.P[(base + p0 + p) * nuo + rank] = (lane < n) ? (y0 + y1) * dk : 0.0;
       }
-      if (lane < nuo) a.P[(base + p) * nuo + rank] = (lane < n) ? (y0 + y1) * dk : 0.0;
     }
   }
 }
