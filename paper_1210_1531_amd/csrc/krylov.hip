@@ -564,15 +564,24 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
 #pragma unroll
           for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
           // q_{k+1} into its register column.  k is uniform, so each test is a
-          // scalar branch; testing bits of a mask keeps the compiler from turning
-          // the chain into a switch whose merge copies every column
-          const unsigned long long sel = 1ull << (k + 1);
+          // scalar branch: first the group of eight columns, then the column
+          // inside it (a dozen scalar tests instead of one per column; the
+          // empty asm statements keep the compiler from turning the tests into
+          // selects or a switch whose merge copies every column)
+          const int cn = k + 1;
 #pragma unroll
-          for (int i = 1; i < NU; ++i) {
-            if (sel & (1ull << i)) {
-              __asm__ volatile("");  // keep the branch (no speculation into selects)
+          for (int g = 0; g < (NU + 7) / 8; ++g) {
+            if ((cn >> 3) == g) {
+              __asm__ volatile("");
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr) qv[rr][i] = w[rr];
+              for (int t = 0; t < 8; ++t) {
+                const int i = g * 8 + t;
+                if (i >= 1 && i < NU && (cn & 7) == t) {
+                  __asm__ volatile("");  // keep the branch (no speculation into selects)
+#pragma unroll
+                  for (int rr = 0; rr < R; ++rr) qv[rr][i] = w[rr];
+                }
+              }
             }
           }
 #pragma unroll
