@@ -76,6 +76,20 @@ def _min_image_dist2(pos: np.ndarray, centre: np.ndarray, cell: np.ndarray) -> n
     return np.einsum("ij,ij->i", d, d)
 
 
+def _void_candidates(centre: np.ndarray, radius: float, cells, a: float) -> np.ndarray:
+    """Sites of the conventional cells that can lie within `radius` of `centre`
+    (periodic wrap, two cells of margin); every other site is farther away."""
+    axes = []
+    for ax in range(3):
+        n = int(cells[ax])
+        lo = int(np.floor((centre[ax] - radius) / a)) - 2
+        hi = int(np.floor((centre[ax] + radius) / a)) + 2
+        axes.append(np.arange(n) if hi - lo + 1 >= n else np.unique(np.mod(np.arange(lo, hi + 1), n)))
+    ix, iy, iz = np.meshgrid(*axes, indexing="ij")
+    cell_id = ((ix * int(cells[1]) + iy) * int(cells[2]) + iz).ravel()
+    return (cell_id[:, None] * _BASIS.shape[0] + np.arange(_BASIS.shape[0])[None, :]).ravel()
+
+
 def make_structure(
     cells=(2, 2, 2),
     a: float = A_DIAMOND,
@@ -98,7 +112,10 @@ def make_structure(
         while n_sites - int(keep.sum()) < target:
             centre = rng.uniform(0.0, 1.0, size=3) * cell
             radius = rng.uniform(void_radius[0], void_radius[1])
-            keep &= _min_image_dist2(pos, centre, cell) > radius * radius
+            # only the sites near the void are tested (the same distance test,
+            # so the structure is the one a test of every site gives)
+            cand = _void_candidates(centre, radius, cells, a)
+            keep[cand] &= _min_image_dist2(pos[cand], centre, cell) > radius * radius
             n_voids += 1
     idx = np.nonzero(keep)[0]
     n_vac = 0
