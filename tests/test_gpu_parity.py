@@ -248,6 +248,70 @@ def test_sampled_columns_at_full_size_void_cell(nu):
     assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
 
 
+def test_sampled_columns_at_full_size_million_site_cell():
+    # the 64x64x32 cell (voids and 3% vacancies, 915k atoms, 3.66M columns):
+    # the full forward and force backward on the GPU (Krylov columns recomputed
+    # in pass 2, scratch in chunks), a sample of columns against the oracle one
+    # by one, and invariants at full size
+    import time
+    import torch
+    from oracle import krylov, neighbors
+    from paper_1210_1531_amd import model
+    import gen
+    s = gen.make(5)
+    log(f"[config5] {s.n_atoms} atoms")
+    ctx = gpu_context(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    st = ctx.stats()
+    log(f"[config5] forward {t_fwd:.2f} s ({4 * s.n_atoms / t_fwd:.3e} columns/s), "
+        f"workflow {st['workflow_used']}, device bytes {st['device_bytes'] / 1e9:.1f} GB")
+    F = ctx.forces(model.sk_model())
+    assert torch.isfinite(F).all()
+    fsum = F.sum(dim=0).abs().max().item()
+    log(f"[config5] |sum F| {fsum:.3e}, max |F| {F.abs().max().item():.3e}")
+    assert fsum < 1e-6
+    eps_d, w_d, nu_d = ctx.spectra()
+    rho_d, _ = ctx.density_matrix()
+    # closure of every column's weights, electron count
+    mask = torch.arange(w_d.shape[1], device=w_d.device)[None, :] < nu_d[:, None].long()
+    sums = torch.where(mask, w_d, torch.zeros_like(w_d)).sum(dim=1)
+    assert (sums - 2.0).abs().max().item() < 1e-11
+    dN = abs(ctx.energy()["N"] - s.n_electrons)
+    log(f"[config5] |N - Ne| {dN:.3e}")
+    assert dN < 1e-6
+    rowptr = np_(ctx._csr[0])
+    colind_d = ctx._csr[1]
+    ptr, atoms = (np_(x) for x in ctx.get_clusters())
+    sizes = np.diff(ptr)
+    rng = np.random.default_rng(5)
+    atoms_pick = np.unique(np.concatenate([np.argsort(sizes)[:2], np.argsort(sizes)[-2:],
+                                           rng.choice(s.n_atoms, 4, replace=False)]))
+    worst = 0.0
+    for J in atoms_pick:
+        clus = neighbors.cluster_of(s.pos, s.cell, int(J), s.r_cluster)
+        np.testing.assert_array_equal(clus, atoms[ptr[J]:ptr[J + 1]])
+        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
+        jl = int(np.searchsorted(clus, J))
+        for a in range(4):
+            j = 4 * int(J) + a
+            res = krylov.column_mode_k(Hc, Sc, 4 * jl + a, s.nu)
+            assert res.nu_eff == int(nu_d[j])
+            np.testing.assert_allclose(np_(eps_d[j])[:res.nu_eff], res.eps, rtol=0, atol=1e-9)
+            np.testing.assert_allclose(np_(w_d[j])[:res.nu_eff], res.w, rtol=0, atol=1e-10)
+            col, _ = krylov.density_column(res, mu, s.kT)
+            lo, hi = int(rowptr[j]), int(rowptr[j + 1])
+            ci = np_(colind_d[lo:hi])
+            rows = np.searchsorted(clus, ci // 4) * 4 + ci % 4
+            worst = max(worst, np.abs(np_(rho_d[lo:hi]) - col[rows]).max())
+    log(f"[config5] sampled {len(atoms_pick)} atoms (sizes {sizes.min()}-{sizes.max()}), "
+        f"max |d rho| {worst:.3e}")
+    assert worst <= RHO_TOL
+
+
 def test_green_and_cluster_columns_match_oracle():
     from oracle import krylov, neighbors
     import gen
