@@ -281,6 +281,18 @@ def main(argv=None):
             "fp64_frac": fp64_tflops / FP64_PEAK_TFLOPS,
         },
     }
+    # ICOHP per block of the pattern (the next row after the hot path): one
+    # thread per block, reading rho (128 B), the H block (128 B), the column
+    # index and two positions, writing three values
+    ctx.icohp(sk)
+    ic = []
+    for _ in range(3):
+        ctx.icohp(sk)
+        ic.append(ctx.stats()["t_icohp_ms"])
+    nblk = ctx.nnz // 16
+    t_ic = sorted(ic)[1]
+    out["icohp"] = {"ms": t_ic, "blocks": nblk,
+                    "GB_per_s": nblk * (128 + 128 + 4 + 48 + 24) / (t_ic * 1e-3) / 1e9}
     if args.copy_probe:
         a = torch.full((64 * 1024 * 1024,), 1.0, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

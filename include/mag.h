@@ -290,6 +290,23 @@ int mag_backward(mag_ctx* ctx, double gA, double* dAdH_csr, double* dAdS_csr,
  * layout of mag_sk_build. */
 int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind);
 
+/* Integrated crystal orbital Hamiltonian populations (Eqs. 4-8) of the last
+ * solve, one value per 4x4 block of the pattern, in block-CSR order (block t
+ * of block row J, whose column atom K is the t-th atom of row J's CSR
+ * blocks; nnz / 16 values per array):
+ *   B[b]       = sum_ab H_{Ja;Kb} rho_{Kb;Ja}  (Eq. 5: the COHP integrated
+ *                against f, through rho of Eq. 2; spin factor 2 as in rho),
+ *   B_sigma[b] = the same with H replaced by its sigma part,
+ *   B_pi[b]    = ... by its pi part (the V_pp_pi term of the p-p sub-block),
+ * the split taken from the two-center blocks of `model` at the system's
+ * positions; B_sigma = B_pi = 0 on the diagonal blocks.  The sum of B over
+ * all blocks is E_band (Eq. 6), and B = B_sigma + B_pi on the off-diagonal
+ * blocks when H is the model's (Eq. 8).  Any output may be NULL (not all).
+ * Requires mag_system.pos; runs pass 2 if needed.  Errors: MAG_EINVAL for a
+ * bad model, no outputs or no positions; MAG_ESTATE before a solve. */
+int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigma,
+              double* B_pi, int mem_kind);
+
 /* ---------------------------------------------------------------------- */
 /* diagnostics                                                              */
 /* ---------------------------------------------------------------------- */
@@ -314,6 +331,7 @@ typedef struct {
   int32_t krylov_buckets;  /* cluster-size buckets (workgroup shapes) of the last pass 1 */
   int32_t krylov_tpb;      /* threads per workgroup of the largest bucket's plan */
   double autotune_ms;      /* time spent timing launch plans (first use of a shape) */
+  double t_icohp_ms;       /* last mag_icohp (after pass 2) */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

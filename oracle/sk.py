@@ -129,6 +129,17 @@ def pair_blocks(d: np.ndarray, p: SKParams = CARBON):
     return two_center(d, p.hopping(), p), two_center(d, p.overlap(), p)
 
 
+def hopping_sigma_pi(d: np.ndarray, p: SKParams = CARBON):
+    """(H_sigma, H_pi): the H block between distinct atoms split by bond type,
+    as the sigma/pi crystal orbital Hamiltonian population needs it (the
+    decomposition stated before Eq. 7).  The pi part is the V_pp_pi term of the
+    p-p sub-block; the sigma part holds the V_ss, V_sp and V_pp_sigma terms.
+    two_center is linear in the bond integrals, so the parts are the block with
+    the other integrals set to zero."""
+    vss, vsp, vpps, vppp = p.hopping()
+    return (two_center(d, (vss, vsp, vpps, 0.0), p), two_center(d, (0.0, 0.0, 0.0, vppp), p))
+
+
 def pair_block_grads(d: np.ndarray, p: SKParams = CARBON):
     """(dH/dd, dS/dd), each (3, 4, 4)."""
     return two_center_grad(d, p.hopping(), p), two_center_grad(d, p.overlap(), p)

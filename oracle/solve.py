@@ -202,6 +202,40 @@ def forces(sysm: System, rho, pi):
     return -dA
 
 
+def icohp(sysm: System, rho):
+    """Integrated crystal orbital Hamiltonian populations, Eqs. 4-8.
+
+    The COHP of Eq. 4 integrated against f (Eq. 5) is, through Eq. 2, a sum of
+    H times rho over the orbitals of the atom pair.  For block t of block row J
+    (column atom K): B = sum_ab H_{Ja;Kb} rho_{Kb;Ja}, with rho in the CSR
+    layout of H (entry (Ja, Kb) holds rho_{Kb;Ja}, from column Ja).  B_sigma
+    and B_pi replace H by its sigma and pi parts (Eq. 8); they are zero on the
+    diagonal blocks, which carry on-site terms only.  Returns three arrays in
+    block-CSR order.
+    """
+    H = sysm.H
+    B, Bs, Bp = [], [], []
+    for J in range(sysm.n_atoms):
+        ks = sysm.rows[J]
+        for t, K in enumerate(ks):
+            hb = np.zeros((NORB, NORB))
+            rb = np.zeros((NORB, NORB))
+            for a in range(NORB):
+                base = H.indptr[NORB * J + a] + NORB * t
+                hb[a] = H.data[base:base + NORB]
+                rb[a] = rho[base:base + NORB]
+            B.append(float(np.sum(hb * rb)))
+            if K == J:
+                Bs.append(0.0)
+                Bp.append(0.0)
+            else:
+                d = _nb.min_image(sysm.pos[K] - sysm.pos[J], sysm.cell)
+                hs, hp = _sk.hopping_sigma_pi(d, sysm.params)
+                Bs.append(float(np.sum(hs * rb)))
+                Bp.append(float(np.sum(hp * rb)))
+    return np.array(B), np.array(Bs), np.array(Bp)
+
+
 @dataclass
 class Result:
     mu: float

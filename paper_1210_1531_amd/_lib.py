@@ -93,6 +93,7 @@ class MagStats(C.Structure):
         ("krylov_buckets", C.c_int32),
         ("krylov_tpb", C.c_int32),
         ("autotune_ms", C.c_double),
+        ("t_icohp_ms", C.c_double),
     ]
 
 
@@ -125,6 +126,7 @@ PROTOTYPES = {
     "mag_green_columns": (I, [CTX, C.POINTER(MagOpts), P, I64, P, I, P, P, I]),
     "mag_backward": (I, [CTX, D, P, P, I]),
     "mag_forces": (I, [CTX, C.POINTER(MagSKModel), P, I]),
+    "mag_icohp": (I, [CTX, C.POINTER(MagSKModel), P, P, P, I]),
     "mag_get_stats": (I, [CTX, C.POINTER(MagStats)]),
 }
 

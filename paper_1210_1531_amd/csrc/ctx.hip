@@ -1639,6 +1639,36 @@ int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind)
   return take_errors(ctx, "mag_forces");
 }
 
+int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigma,
+              double* B_pi, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!model_ok(model)) return fail(ctx, MAG_EINVAL, "invalid Slater-Koster model");
+  if (!B && !B_sigma && !B_pi) return fail(ctx, MAG_EINVAL, "no output requested");
+  if (!ctx->has_pos) return fail(ctx, MAG_EINVAL, "ICOHP needs mag_system.pos");
+  TRY(ensure_density(ctx));
+  const int64_t nblk = ctx->nnz / 16;
+  double* dst[3] = {B, B_sigma, B_pi};
+  DevBuf out;
+  if (mem_kind == MAG_HOST) {
+    ALLOC(out, sizeof(double) * 3 * std::max<int64_t>(nblk, 1));
+    for (int q = 0; q < 3; ++q)
+      if (dst[q]) dst[q] = out.as<double>() + q * nblk;
+  }
+  Timer tm(ctx->stream);
+  HIPCHK(launch_icohp(to_dev(*model), ctx->pos.as<double>(), ctx->N, nblk, ctx->cell,
+                      ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(), ctx->bval.as<double>(),
+                      ctx->rho.as<double>(), dst[0], dst[1], dst[2], ctx->stream));
+  if (mem_kind == MAG_HOST) {
+    double* host[3] = {B, B_sigma, B_pi};
+    for (int q = 0; q < 3; ++q)
+      if (host[q]) TRY(copy_out(ctx, host[q], dst[q], sizeof(double) * nblk, MAG_HOST));
+  }
+  TRY(sync(ctx));
+  ctx->stats.t_icohp_ms = tm.stop_ms();
+  return take_errors(ctx, "mag_icohp");
+}
+
 int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
   if (!ctx || !out) return MAG_EINVAL;
   int64_t bytes = 0;

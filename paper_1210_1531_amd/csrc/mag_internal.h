@@ -228,6 +228,10 @@ hipError_t launch_sk_csr(const int32_t* bptr, const int32_t* bcol, int64_t n, in
 hipError_t launch_sk_values(const SKModelDev& m, const double* pos, int64_t n,
                             const double cell[3], const int32_t* bptr, const int32_t* bcol,
                             double* H, double* S, hipStream_t s);
+hipError_t launch_icohp(const SKModelDev& m, const double* pos, int64_t n, int64_t nblk,
+                        const double cell[3], const int32_t* bptr, const int32_t* bcol,
+                        const double* bval, const double* rho, double* B, double* Bsig,
+                        double* Bpi, hipStream_t s);
 hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
                          const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
                          const double* gH, const double* gS, double sign_gS, double* grad,

@@ -264,6 +264,81 @@ __device__ __forceinline__ void two_center_contract(const SKModelDev& m, const d
   }
 }
 
+// the same block split by bond type: sigma (V_ss, V_sp, V_pp sigma terms)
+// and pi (the V_pp pi term of the p-p sub-block); Bs + Bp is two_center's block
+__device__ __forceinline__ void two_center_split(const SKModelDev& m, const double* V, double dx,
+                                                 double dy, double dz, double Bs[4][4],
+                                                 double Bp[4][4]) {
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double l[3] = {dx / r, dy / r, dz / r};
+  double u, du;
+  radial(m, r, u, du);
+  Bs[0][0] = V[0] * u;
+  Bp[0][0] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    Bs[0][1 + a] = l[a] * V[1] * u;
+    Bs[1 + a][0] = -l[a] * V[1] * u;
+    Bp[0][1 + a] = 0.0;
+    Bp[1 + a][0] = 0.0;
+    for (int b = 0; b < 3; ++b) {
+      const double ll = l[a] * l[b];
+      Bs[1 + a][1 + b] = ll * V[2] * u;
+      Bp[1 + a][1 + b] = ((a == b ? 1.0 : 0.0) - ll) * V[3] * u;
+    }
+  }
+}
+
+// integrated crystal orbital Hamiltonian populations per block of the pattern:
+// block t of block row J (column atom K) gives B = sum_ab H_{Ja;Kb} rho_{Kb;Ja}
+// from the system's H (block values) and rho (CSR layout of H), and its sigma
+// and pi parts from the split SK block at the positions (zero on the diagonal).
+// One thread per block; its row J by binary search in the block-row pointers.
+__global__ void icohp_kernel(SKModelDev m, const double* pos, int64_t n, int64_t nblk, Box box,
+                             const int32_t* bptr, const int32_t* bcol, const double* bval,
+                             const double* rho, double* B, double* Bsig, double* Bpi) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  int64_t lo = 0, hi = n - 1;  // last row J with bptr[J] <= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (bptr[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t J = lo;
+  const int64_t b0 = bptr[J];
+  const int nb = bptr[J + 1] - bptr[J];
+  const int t = (int)(b - b0);
+  const int K = bcol[b];
+  const double* hv = bval + b * 32;  // H: quarters of row pairs (see to_blocks)
+  double rb[4][4];
+  double full = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    const double2* rr = reinterpret_cast<const double2*>(rho + 16 * b0 + 4 * (int64_t)a * nb + 4 * t);
+    const double2 r01 = rr[0], r23 = rr[1];
+    rb[a][0] = r01.x;
+    rb[a][1] = r01.y;
+    rb[a][2] = r23.x;
+    rb[a][3] = r23.y;
+    for (int c = 0; c < 4; ++c) full = fma(hv[(c >> 1) * 8 + 2 * a + (c & 1)], rb[a][c], full);
+  }
+  double sig = 0.0, pi = 0.0;
+  if (K != J) {
+    double dx = pos[3 * K] - pos[3 * J], dy = pos[3 * K + 1] - pos[3 * J + 1],
+           dz = pos[3 * K + 2] - pos[3 * J + 2];
+    min_image(box, dx, dy, dz);
+    double Bs[4][4], Bp[4][4];
+    two_center_split(m, m.vh, dx, dy, dz, Bs, Bp);
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        sig = fma(Bs[a][c], rb[a][c], sig);
+        pi = fma(Bp[a][c], rb[a][c], pi);
+      }
+  }
+  if (B) B[b] = full;
+  if (Bsig) Bsig[b] = sig;
+  if (Bpi) Bpi[b] = pi;
+}
+
 __global__ void sk_values_kernel(SKModelDev m, const double* pos, int64_t n, Box box,
                                  const int32_t* bptr, const int32_t* bcol, double* H, double* S) {
   const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -384,6 +459,17 @@ hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, cons
   Box box{{cell[0], cell[1], cell[2]}};
   hipLaunchKernelGGL(sk_vjp_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, m, pos, n, box,
                      bptr, bcol, btrans, gH, gS, sign_gS, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_icohp(const SKModelDev& m, const double* pos, int64_t n, int64_t nblk,
+                        const double cell[3], const int32_t* bptr, const int32_t* bcol,
+                        const double* bval, const double* rho, double* B, double* Bsig,
+                        double* Bpi, hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  if (n <= 0 || nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(icohp_kernel, dim3(blocks_for(nblk, STPB)), dim3(STPB), 0, s, m, pos, n, nblk,
+                     box, bptr, bcol, bval, rho, B, Bsig, Bpi);
   return hipGetLastError();
 }
 

@@ -282,6 +282,14 @@ class Context:
         self._check(self._lib.mag_forces(self._h, C.byref(model), ptrs[0], kind))
         return outs[0]
 
+    def icohp(self, model):
+        """(B, B_sigma, B_pi) per 4x4 block of the pattern, in block-CSR order
+        (Eqs. 4-8; see mag_icohp)."""
+        nblk = self.nnz // 16
+        outs, ptrs, kind = self._outputs([((nblk,), np.float64)] * 3)
+        self._check(self._lib.mag_icohp(self._h, C.byref(model), ptrs[0], ptrs[1], ptrs[2], kind))
+        return outs
+
     def stats(self):
         s = L.MagStats()
         self._check(self._lib.mag_get_stats(self._h, C.byref(s)))

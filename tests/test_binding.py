@@ -71,6 +71,7 @@ def test_every_method_matches_the_prototypes(ctx, monkeypatch):
     ctx.green_columns([0], [0.5 + 0.1j], nu=8, kT=0.1)
     ctx.backward(1.0)
     ctx.forces(model.sk_model())
+    ctx.icohp(model.sk_model())
     ctx.stats()
     called = set(ctx._lib.calls)
     expected = set(L.PROTOTYPES) - {"mag_create", "mag_destroy", "mag_version", "mag_opts_default",

@@ -312,6 +312,51 @@ def test_sampled_columns_at_full_size_million_site_cell():
     assert worst <= RHO_TOL
 
 
+# |d B| <= 16 |H|max |d rho|: the rho bar times sixteen entries of at most 6 eV
+ICOHP_TOL = 1e-8
+
+
+@pytest.mark.parametrize("key", [1, "mini_vac"])
+def test_icohp_matches_oracle(key):
+    from oracle import solve
+    from paper_1210_1531_amd import model
+    s, sysm = oracle_system(key)
+    ref = oracle_solution(key)
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    B, Bs, Bp = (np_(x) for x in ctx.icohp(model.sk_model()))
+    Bo, Bso, Bpo = solve.icohp(sysm, ref.rho)
+    d = max(np.abs(B - Bo).max(), np.abs(Bs - Bso).max(), np.abs(Bp - Bpo).max())
+    log(f"[icohp {key}] blocks {B.size}, max |dB| {d:.3e}, sum B - E_band {B.sum() - E:.3e}")
+    np.testing.assert_allclose(B, Bo, rtol=0, atol=ICOHP_TOL)
+    np.testing.assert_allclose(Bs, Bso, rtol=0, atol=ICOHP_TOL)
+    np.testing.assert_allclose(Bp, Bpo, rtol=0, atol=ICOHP_TOL)
+    # Eq. 6 on the GPU's own numbers
+    assert abs(B.sum() - E) < 1e-10 * abs(E)
+
+
+def test_icohp_sum_rule_at_full_size():
+    # the benchmark cell: Eq. 6 and Eq. 8 on every block
+    from paper_1210_1531_amd import model
+    import gen
+    s = gen.make(2)
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    B, Bs, Bp = (np_(x) for x in ctx.icohp(model.sk_model()))
+    # block (J, t) of the pattern: column atom = colind of row 4J at 4t, over 4
+    rowptr = np_(ctx._csr[0])
+    colind = np_(ctx._csr[1])
+    row_atom = np.repeat(np.arange(s.n_atoms), np.diff(rowptr[::4]) // 16)
+    first = np.concatenate([np.arange(rowptr[4 * J], rowptr[4 * J + 1], 4)
+                            for J in range(s.n_atoms)])
+    diag = colind[first] // 4 == row_atom
+    log(f"[icohp config2] blocks {B.size}, sum B - E_band {B.sum() - E:.3e}")
+    assert B.size == first.size and diag.sum() == s.n_atoms
+    assert abs(B.sum() - E) < 1e-10 * abs(E)
+    np.testing.assert_allclose((Bs + Bp)[~diag], B[~diag], rtol=0, atol=1e-11)
+    assert np.all(Bs[diag] == 0.0) and np.all(Bp[diag] == 0.0)
+
+
 def test_green_and_cluster_columns_match_oracle():
     from oracle import krylov, neighbors
     import gen
