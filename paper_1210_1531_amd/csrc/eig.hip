@@ -40,10 +40,22 @@ int eig_rec_cap(int cap) { return 2 * cap * cap; }
 int eig_sweep_cap(int cap) { return std::min(4 * cap, 128); }  // two header registers per lane
 
 // ---------------------------------------------------------------------------
-// 1. Cholesky, C = L^-1 h L^-T, Householder tridiagonalization
+// 1. Cholesky, C = L^-1 h L^-T, Householder tridiagonalization.  Lane i keeps
+// row i of s (then of L) and row i of h (then column i of Y = L^-1 h and of C)
+// in registers; every step below is unrolled over the capacity NM, so each
+// register index is a compile-time constant, and the values one lane needs
+// from another come by v_readlane (a constant lane index).
+
+// value of lane `src` (compile-time) in every lane
+__device__ __forceinline__ double bcast(double v, int src) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
+                          __builtin_amdgcn_readlane(__double2loint(v), src));
+}
+
 template <int NM>
 __global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
-  extern __shared__ double sm[];
+  extern __shared__ double sm[];  // NM x (NM + 1): transposes
+  constexpr int LD = NM + 1;
   const int64_t slot = blockIdx.x;
   if (slot >= a.ncols) return;
   const int lane = threadIdx.x;
@@ -52,137 +64,159 @@ __global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
     if (n > NM && lane == 0) atomicOr(a.err, (int)KERR_CAPACITY);
     return;
   }
-  const int ld = n + 1;
-  double* A = sm;               // n x ld: h, then C
-  double* L = A + n * ld;       // n x ld: Cholesky factor below, reflectors above
-  double* vv = L + n * ld;      // Householder vector
-  double* ww = vv + NM;         // Householder update vector
-  double* li = ww + NM;         // 1 / L_ii
-  int* flag = reinterpret_cast<int*>(li + NM);
   double* h = a.hs + slot * (int64_t)(2 * NM * NM);
   double* s = h + NM * NM;
   double* tr = a.trid + slot * (int64_t)(4 * NM);
+  const bool row = lane < n;
 
-  for (int idx = lane; idx < n * n; idx += ETPB) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    const int lo = min(i, k), hi = max(i, k);
-    A[i * ld + k] = h[hi * NM + lo];
-    L[i * ld + k] = s[hi * NM + lo];
+  // rows `lane` of s and h (upper triangles: element (i, k), i <= k, at k * NM + i)
+  double L[NM], X[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    const int lo = min(lane, t), hi = max(lane, t);
+    const bool in = row && t < n;
+    L[t] = in ? s[hi * NM + lo] : 0.0;
+    X[t] = in ? h[hi * NM + lo] : 0.0;
   }
-  if (lane < n) tr[3 * NM + lane] = s[lane * NM];  // s e_1 (s_{i0} = s_{0i})
-  if (lane == 0) flag[0] = 0;
-  __syncthreads();
+  if (row) tr[3 * NM + lane] = L[0];  // s e_1
 
-  // ---- Cholesky s = L L^T (lower triangle of L)
-  for (int c = 0; c < n; ++c) {
-    if (lane == 0) {
-      double d = L[c * ld + c];
-      for (int p = 0; p < c; ++p) d -= L[c * ld + p] * L[c * ld + p];
+  // ---- Cholesky s = L L^T, column c after column c: row c comes from lane c
+  bool notpd = false;
+  double linv = 0.0;  // 1 / L[lane][lane]
+#pragma unroll
+  for (int c = 0; c < NM; ++c) {
+    if (c < n) {
+      double acc = L[c];
+#pragma unroll
+      for (int p = 0; p < c; ++p) acc = fma(-L[p], bcast(L[p], c), acc);
+      double d = bcast(acc, c);
       if (!(d > 0.0)) {
-        flag[0] = 1;
+        notpd = true;
         d = 1.0;
       }
-      const double r = sqrt(d);
-      L[c * ld + c] = r;
-      li[c] = 1.0 / r;
+      const double r = sqrt(d), ri = 1.0 / r;
+      if (lane == c) linv = ri;
+      L[c] = (lane == c) ? r : ((lane > c) ? acc * ri : 0.0);
     }
-    __syncthreads();
-    if (lane > c && lane < n) {
-      double x = L[lane * ld + c];
-      for (int p = 0; p < c; ++p) x -= L[lane * ld + p] * L[c * ld + p];
-      L[lane * ld + c] = x * li[c];
-    }
-    __syncthreads();
   }
-  if (flag[0] && lane == 0) atomicOr(a.err, (int)KERR_NOTPD);
+  if (notpd && lane == 0) atomicOr(a.err, (int)KERR_NOTPD);
 
-  // ---- X = L^-1 h, column `lane` in place; then C = X L^-T, row `lane` in place
-  if (lane < n) {
-    for (int i = 0; i < n; ++i) {
-      double x = A[i * ld + lane];
-      for (int p = 0; p < i; ++p) x -= L[i * ld + p] * A[p * ld + lane];
-      A[i * ld + lane] = x * li[i];
+  // ---- Y = L^-1 h: lane k solves for column k (row k of the symmetric h)
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    if (i < n) {
+      double acc = X[i];
+#pragma unroll
+      for (int p = 0; p < i; ++p) acc = fma(-bcast(L[p], i), X[p], acc);
+      X[i] = acc * bcast(linv, i);
     }
   }
-  __syncthreads();
-  if (lane < n) {
-    double* row = A + lane * ld;
-    for (int i = 0; i < n; ++i) {
-      double x = row[i];
-      for (int p = 0; p < i; ++p) x -= L[i * ld + p] * row[p];
-      row[i] = x * li[i];
-    }
+  // row k of Y through LDS, then C = L^-1 Y^T column by column
+  if (lane < NM) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t) sm[t * LD + lane] = X[t];
   }
   __syncthreads();
-  for (int idx = lane; idx < n * n; idx += ETPB) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    if (i < k) {
-      const double v = 0.5 * (A[i * ld + k] + A[k * ld + i]);
-      A[i * ld + k] = v;
-      A[k * ld + i] = v;
-    }
+  if (lane < NM) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t) X[t] = sm[lane * LD + t];
   }
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    if (i < n) {
+      double acc = X[i];
+#pragma unroll
+      for (int p = 0; p < i; ++p) acc = fma(-bcast(L[p], i), X[p], acc);
+      X[i] = acc * bcast(linv, i);
+    }
+  }
+  // symmetrize: C = (C + C^T) / 2, lane k keeping column k
+  if (lane < NM) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t) sm[t * LD + lane] = X[t];
+  }
+  __syncthreads();
+  if (lane < NM) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t) X[t] = 0.5 * (X[t] + sm[lane * LD + t]);
+  }
+  // L (zero above the diagonal) over h
+  if (row) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t)
+      if (t < n) h[lane * NM + t] = (t <= lane) ? L[t] : 0.0;
+  }
 
-  // ---- Householder: step k reflects rows and columns k+1..n-1 so that column
-  // k vanishes below the subdiagonal.  Lane i owns column i of the trailing
-  // block (C stays symmetric, so C v is taken column-wise).
-  for (int k = 0; k + 2 < n; ++k) {
-    const double x0 = A[k * ld + k + 1];
-    const double xi = (lane > k + 1 && lane < n) ? A[k * ld + lane] : 0.0;
-    const double sig = wave_allreduce(xi * xi);
-    double beta = 0.0, v0 = 1.0, sub = x0;
-    if (sig > 0.0) {
-      const double mu = sqrt(x0 * x0 + sig);
-      v0 = (x0 <= 0.0) ? x0 - mu : -sig / (x0 + mu);
-      beta = 2.0 * v0 * v0 / (sig + v0 * v0);
-      sub = mu;
-    }
-    const double vi = (lane == k + 1) ? 1.0 : xi / v0;  // zero outside k+1..n-1
-    if (lane < NM) vv[lane] = (lane > k && lane < n) ? vi : 0.0;
-    if (lane > k + 1 && lane < n) L[k * ld + lane] = vi;  // strictly upper part of L
-    if (lane == 0) {
-      tr[k] = A[k * ld + k];
-      tr[NM + k] = sub;
-      tr[2 * NM + k] = beta;
-    }
-    __syncthreads();
-    if (beta != 0.0) {
-      // p = beta C v, w = p - (beta p^T v / 2) v
-      double p = 0.0;
-      if (lane > k && lane < n) {
-        for (int i = k + 1; i < n; ++i) p = fma(A[i * ld + lane], vv[i], p);
-        p *= beta;
+  // ---- Householder: step j reflects rows and columns j+1..n-1 so that column
+  // j vanishes below the subdiagonal (Golub & Van Loan's house vector,
+  // v[j+1] = 1).  Lane k keeps column k of the trailing block; C is symmetric,
+  // so lane i's entry j is C[j][i] = C[i][j], its own part of column j.
+#pragma unroll
+  for (int j = 0; j + 2 < NM; ++j) {
+    if (j + 2 < n) {
+      const double x0 = bcast(X[j], j + 1);
+      const double xi = (lane > j + 1 && row) ? X[j] : 0.0;
+      const double sig = wave_allreduce(xi * xi);
+      double beta = 0.0, v0 = 1.0, sub = x0;
+      if (sig > 0.0) {
+        const double mu = sqrt(x0 * x0 + sig);
+        v0 = (x0 <= 0.0) ? x0 - mu : -sig / (x0 + mu);
+        beta = 2.0 * v0 * v0 / (sig + v0 * v0);
+        sub = mu;
       }
-      const double kk = 0.5 * beta * wave_allreduce((lane > k && lane < n) ? p * vv[lane] : 0.0);
-      const double wi = p - kk * ((lane > k && lane < n) ? vv[lane] : 0.0);
-      if (lane < NM) ww[lane] = (lane > k && lane < n) ? wi : 0.0;
-      __syncthreads();
-      if (lane > k && lane < n) {
-        const double vl = vv[lane];
-        for (int i = k + 1; i < n; ++i) A[i * ld + lane] -= vv[i] * wi + ww[i] * vl;
+      const bool act = lane > j && row;                          // rows j+1..n-1
+      const double vi = act ? ((lane == j + 1) ? 1.0 : xi / v0) : 0.0;
+      if (lane == j) {
+        tr[j] = X[j];
+        tr[NM + j] = sub;
+        tr[2 * NM + j] = beta;
       }
-      __syncthreads();
+      if (row) s[j * NM + lane] = vi;  // dense reflector row j
+      if (beta != 0.0) {
+        // p = beta C v (lane k: its column against v), w = p - (beta p^T v / 2) v
+        double vb[NM];
+        double p = 0.0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+          vb[i] = 0.0;
+          if (i > j && i < n) {
+            vb[i] = bcast(vi, i);
+            p = fma(X[i], vb[i], p);
+          }
+        }
+        p = act ? beta * p : 0.0;
+        const double kk = 0.5 * beta * wave_allreduce(p * vi);
+        const double wi = p - kk * vi;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+          if (i > j && i < n) {
+            const double wb = bcast(wi, i);
+            if (act) X[i] -= vb[i] * wi + wb * vi;
+          }
+        }
+      }
     }
   }
-  if (lane == 0) {
-    if (n >= 2) {
-      tr[n - 2] = A[(n - 2) * ld + n - 2];
-      tr[NM + n - 2] = A[(n - 2) * ld + n - 1];
-      tr[2 * NM + n - 2] = 0.0;
+  // the last 2 x 2 block (or 1 x 1)
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    if (t + 2 == n) {
+      const double dd = bcast(X[t], t), ee = bcast(X[t], t + 1);
+      if (lane == 0) {
+        tr[t] = dd;
+        tr[NM + t] = ee;
+        tr[2 * NM + t] = 0.0;
+      }
     }
-    tr[n - 1] = A[(n - 1) * ld + n - 1];
-    tr[NM + n - 1] = 0.0;
-    tr[2 * NM + n - 1] = 0.0;
-  }
-  __syncthreads();
-  // L (zero above the diagonal) over h; dense reflector rows over s
-  for (int idx = lane; idx < n * n; idx += ETPB) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    h[i * NM + k] = (k <= i) ? L[i * ld + k] : 0.0;
-    double v = 0.0;
-    if (i + 2 < n) v = (k == i + 1) ? 1.0 : ((k > i + 1) ? L[i * ld + k] : 0.0);
-    s[i * NM + k] = v;
+    if (t + 1 == n) {
+      const double dd = bcast(X[t], t);
+      if (lane == 0) {
+        tr[t] = dd;
+        tr[NM + t] = 0.0;
+        tr[2 * NM + t] = 0.0;
+      }
+    }
   }
 }
 
@@ -571,8 +605,7 @@ __global__ __launch_bounds__(ETPB) void vec_fallback_kernel(EigArgs a) {
 template <int NM>
 static hipError_t launch_eig_nm(const EigArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)a.ncols;
-  const size_t lds1 = (size_t)2 * NM * (NM + 1) * sizeof(double) + 3 * NM * sizeof(double) +
-                      4 * sizeof(int);
+  const size_t lds1 = (size_t)NM * (NM + 1) * sizeof(double);
   const size_t lds3 = (size_t)2 * NM * (NM + 1) * sizeof(double) + 4 * NM * sizeof(double);
   hipLaunchKernelGGL(tri_kernel<NM>, dim3(nb), dim3(ETPB), lds1, s, a);
   hipError_t e = launch_fill_i32(a.fb_count, 1, 0, s);
