@@ -307,6 +307,17 @@ int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind)
 int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigma,
               double* B_pi, int mem_kind);
 
+/* Energy-resolved crystal orbital Hamiltonian populations (Eq. 4) of the
+ * last solve, broadened by eta > 0 (z = e + i eta), at ne energies (host
+ * array, eV): for block t of block row J (column atom K),
+ *   C[b * ne + q] = -(g_s / pi) sum_ab H_{Ja;Kb} Im G_{Kb;Ja}(e_q + i eta)
+ * with G the Galerkin columns on the Ritz spectrum, in block-CSR order as in
+ * mag_icohp (nnz / 16 blocks).  Integrated against f(e - mu) it tends to the
+ * ICOHP B as eta -> 0 (Eq. 5).  Needs the pattern rows kept by the store
+ * workflow: MAG_ESTATE after a solve with MAG_WORKFLOW_RECOMPUTE (or before
+ * any solve); MAG_EINVAL for ne <= 0, eta <= 0 or non-finite energies. */
+int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C, int mem_kind);
+
 /* ---------------------------------------------------------------------- */
 /* diagnostics                                                              */
 /* ---------------------------------------------------------------------- */
@@ -332,6 +343,7 @@ typedef struct {
   int32_t krylov_tpb;      /* threads per workgroup of the largest bucket's plan */
   double autotune_ms;      /* time spent timing launch plans (first use of a shape) */
   double t_icohp_ms;       /* last mag_icohp (after pass 2) */
+  double t_cohp_ms;        /* last mag_cohp */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

@@ -236,6 +236,36 @@ def icohp(sysm: System, rho):
     return np.array(B), np.array(Bs), np.array(Bp)
 
 
+def cohp(sysm: System, cd, energies, eta):
+    """Energy-resolved crystal orbital Hamiltonian population, Eq. 4, at
+    z = e + i eta (eta > 0 in place of the limit i0).
+
+    For block t of block row J (column atom K):
+      C(e) = -(g_s / pi) sum_ab H_{Ja;Kb} Im G_{Kb;Ja}(e + i eta),
+    with the Galerkin column G_{Kb;j}(z) = sum_k Y_{Kb,k} d_k / (z - eps_k) of
+    column j = (J, a) (its pattern rows are cd["ypd"]).  g_s = 2 as in rho, so
+    that integrating against f(e - mu) gives the ICOHP of Eq. 5.  Returns an
+    array (blocks in block-CSR order, energies).
+    """
+    H = sysm.H
+    z = np.asarray(energies, dtype=np.float64) + 1j * eta
+    where = {int(j): i for i, j in enumerate(cd["cols"])}
+    out = []
+    for J in range(sysm.n_atoms):
+        for t, _ in enumerate(sysm.rows[J]):
+            acc = np.zeros(z.size)
+            for a in range(NORB):
+                j = NORB * J + a
+                i = where[j]
+                k = cd["nu_eff"][i]
+                G = cd["ypd"][i][NORB * t:NORB * t + NORB, :k] @ (
+                    1.0 / (z[None, :] - cd["eps"][i, :k][:, None]))
+                h = H.data[H.indptr[j] + NORB * t:H.indptr[j] + NORB * t + NORB]
+                acc += -(_kry.G_SPIN / np.pi) * (h @ G).imag
+            out.append(acc)
+    return np.array(out)
+
+
 @dataclass
 class Result:
     mu: float

@@ -94,6 +94,7 @@ class MagStats(C.Structure):
         ("krylov_tpb", C.c_int32),
         ("autotune_ms", C.c_double),
         ("t_icohp_ms", C.c_double),
+        ("t_cohp_ms", C.c_double),
     ]
 
 
@@ -127,6 +128,7 @@ PROTOTYPES = {
     "mag_backward": (I, [CTX, D, P, P, I]),
     "mag_forces": (I, [CTX, C.POINTER(MagSKModel), P, I]),
     "mag_icohp": (I, [CTX, C.POINTER(MagSKModel), P, P, P, I]),
+    "mag_cohp": (I, [CTX, C.POINTER(D), I, D, P, I]),
     "mag_get_stats": (I, [CTX, C.POINTER(MagStats)]),
 }
 

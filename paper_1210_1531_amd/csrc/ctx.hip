@@ -1669,6 +1669,36 @@ int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigm
   return take_errors(ctx, "mag_icohp");
 }
 
+int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!energies || !C || ne <= 0) return fail(ctx, MAG_EINVAL, "energies, ne > 0 and C required");
+  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(ctx, MAG_EINVAL, "eta must be > 0");
+  for (int q = 0; q < ne; ++q)
+    if (!std::isfinite(energies[q])) return fail(ctx, MAG_EINVAL, "energies must be finite");
+  if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve: call mag_solve_columns first");
+  if (ctx->opts.workflow != MAG_WORKFLOW_STORE || !ctx->P.p)
+    return fail(ctx, MAG_ESTATE, "COHP needs the stored pattern rows: solve with MAG_WORKFLOW_STORE");
+  const int64_t nblk = ctx->nnz / 16;
+  DevBuf en, out;
+  ALLOC(en, sizeof(double) * ne);
+  HIPCHK(hipMemcpyAsync(en.p, energies, sizeof(double) * ne, hipMemcpyHostToDevice, ctx->stream));
+  double* dst = C;
+  if (mem_kind == MAG_HOST) {
+    ALLOC(out, sizeof(double) * std::max<int64_t>(1, nblk * ne));
+    dst = out.as<double>();
+  }
+  Timer tm(ctx->stream);
+  HIPCHK(launch_cohp(ctx->bval.as<double>(), ctx->bptr.as<int32_t>(), ctx->N, nblk,
+                     ctx->rowptr.as<int64_t>(), ctx->P.as<double>(), ctx->eps.as<double>(),
+                     ctx->nu_eff.as<int32_t>(), ctx->nu, en.as<double>(), ne, eta, dst,
+                     ctx->stream));
+  if (mem_kind == MAG_HOST) TRY(copy_out(ctx, C, dst, sizeof(double) * nblk * ne, MAG_HOST));
+  TRY(sync(ctx));
+  ctx->stats.t_cohp_ms = tm.stop_ms();
+  return take_errors(ctx, "mag_cohp");
+}
+
 int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
   if (!ctx || !out) return MAG_EINVAL;
   int64_t bytes = 0;

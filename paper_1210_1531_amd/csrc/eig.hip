@@ -747,6 +747,71 @@ __global__ __launch_bounds__(ETPB) void green_kernel(const double* P, int pat_st
   }
 }
 
+// energy-resolved crystal orbital Hamiltonian population (Eq. 4) per block of
+// the pattern, broadened by eta: block t of block row J (column atom K),
+//   C(e) = g_s sum_a sum_k c_ak L(e - eps_{j,k}),  j = 4J + a,
+//   c_ak = sum_b H_{Ja;Kb} P_{Kb,j,k}  (P = Y d on the pattern of column j),
+//   L(x) = (eta / pi) / (x^2 + eta^2)  = -Im 1/(x + i eta) / pi,
+// from the stored pattern rows (P[(rowptr[j] + p) nu + k]) and the Ritz values
+// of the last solve.  One workgroup per block: the 4 nu weights first, then
+// lanes over the energies.
+__global__ __launch_bounds__(ETPB) void cohp_kernel(const double* bval, const int32_t* bptr,
+                                                    int64_t n, int64_t nblk,
+                                                    const int64_t* rowptr, const double* P,
+                                                    const double* eps, const int32_t* nu_eff,
+                                                    int nu, const double* en, int ne, double eta,
+                                                    double* out) {
+  __shared__ double c_s[4 * 48], e_s[4 * 48];
+  const int64_t b = blockIdx.x;
+  if (b >= nblk) return;
+  const int lane = threadIdx.x;
+  int64_t lo = 0, hi = n - 1;  // block row J: last row with bptr[J] <= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (bptr[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t J = lo;
+  const int t = (int)(b - bptr[J]);
+  const double* hv = bval + b * 32;  // H: quarters of row pairs
+  for (int idx = lane; idx < 4 * nu; idx += ETPB) {
+    const int a = idx / nu, k = idx - (idx / nu) * nu;
+    const int64_t j = 4 * J + a;
+    double c = 0.0, e = 0.0;
+    if (k < nu_eff[j]) {
+      const double* pr = P + (rowptr[j] + 4 * t) * nu + k;
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) c = fma(hv[(c4 >> 1) * 8 + 2 * a + (c4 & 1)], pr[c4 * nu], c);
+      e = eps[j * nu + k];
+    }
+    c_s[idx] = c;
+    e_s[idx] = e;
+  }
+  __syncthreads();
+  const double scale = G_SPIN * eta / 3.14159265358979323846;
+  const double eta2 = eta * eta;
+  for (int q = lane; q < ne; q += ETPB) {
+    const double x = en[q];
+    double acc = 0.0;
+    for (int idx = 0; idx < 4 * nu; ++idx) {
+      const double d = x - e_s[idx];
+      acc = fma(c_s[idx], 1.0 / fma(d, d, eta2), acc);
+    }
+    out[b * ne + q] = scale * acc;
+  }
+}
+
+hipError_t launch_cohp(const double* bval, const int32_t* bptr, int64_t n, int64_t nblk,
+                       const int64_t* rowptr, const double* P, const double* eps,
+                       const int32_t* nu_eff, int nu, const double* en, int ne, double eta,
+                       double* out, hipStream_t s) {
+  if (nblk <= 0 || ne <= 0) return hipSuccess;
+  if (nu > 48) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cohp_kernel, dim3((unsigned)nblk), dim3(ETPB), 0, s, bval, bptr, n, nblk,
+                     rowptr, P, eps, nu_eff, nu, en, ne, eta, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_green(const double* P, int pat_stride, const int32_t* cols, int64_t ncols,
                         const int32_t* npat, const int64_t* out_off, const double* eps,
                         const int32_t* nu_eff, int nu, const double* z, int nz, double* out,

@@ -252,6 +252,10 @@ hipError_t launch_cluster_rho(const double* P, int pat_stride, const int32_t* co
                               const int32_t* npat, const int64_t* out_off, const double* eps,
                               const int32_t* nu_eff, int nu, const MuState* st, double* out,
                               hipStream_t s);
+hipError_t launch_cohp(const double* bval, const int32_t* bptr, int64_t n, int64_t nblk,
+                       const int64_t* rowptr, const double* P, const double* eps,
+                       const int32_t* nu_eff, int nu, const double* en, int ne, double eta,
+                       double* out, hipStream_t s);
 hipError_t launch_green(const double* P, int pat_stride, const int32_t* cols, int64_t ncols,
                         const int32_t* npat, const int64_t* out_off, const double* eps,
                         const int32_t* nu_eff, int nu, const double* z, int nz, double* out,

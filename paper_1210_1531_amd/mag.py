@@ -290,6 +290,16 @@ class Context:
         self._check(self._lib.mag_icohp(self._h, C.byref(model), ptrs[0], ptrs[1], ptrs[2], kind))
         return outs
 
+    def cohp(self, energies, eta):
+        """C[block, q]: the COHP of each block of the pattern at energies[q] + i eta
+        (Eq. 4; see mag_cohp).  Needs a solve with workflow="store"."""
+        e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
+        nblk = self.nnz // 16
+        outs, ptrs, kind = self._outputs([((nblk, e.size), np.float64)])
+        self._check(self._lib.mag_cohp(self._h, e.ctypes.data_as(C.POINTER(C.c_double)), e.size,
+                                       float(eta), ptrs[0], kind))
+        return outs[0]
+
     def stats(self):
         s = L.MagStats()
         self._check(self._lib.mag_get_stats(self._h, C.byref(s)))

@@ -72,6 +72,7 @@ def test_every_method_matches_the_prototypes(ctx, monkeypatch):
     ctx.backward(1.0)
     ctx.forces(model.sk_model())
     ctx.icohp(model.sk_model())
+    ctx.cohp([0.0, 1.0], 0.1)
     ctx.stats()
     called = set(ctx._lib.calls)
     expected = set(L.PROTOTYPES) - {"mag_create", "mag_destroy", "mag_version", "mag_opts_default",

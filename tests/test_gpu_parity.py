@@ -335,6 +335,31 @@ def test_icohp_matches_oracle(key):
     assert abs(B.sum() - E) < 1e-10 * abs(E)
 
 
+# |d C| <= 16 |H|max g_s / (pi eta) sum_k |d P_k|: the rho bar scaled by 1 / eta
+COHP_TOL = 1e-7
+
+
+@pytest.mark.parametrize("key", [1, "mini_vac"])
+def test_cohp_matches_oracle(key):
+    from oracle import solve
+    s, sysm = oracle_system(key)
+    ref = oracle_solution(key)
+    ctx = gpu_context(s)
+    ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow="store")
+    e = np.array([-12.0, -7.5, -3.0, 0.0, 2.5, 6.0, 11.0])
+    eta = 0.05
+    C = np_(ctx.cohp(e, eta))
+    Co = solve.cohp(sysm, ref.cd, e, eta)
+    log(f"[cohp {key}] blocks {C.shape[0]}, max |C| {np.abs(Co).max():.3e}, "
+        f"max |dC| {np.abs(C - Co).max():.3e}")
+    np.testing.assert_allclose(C, Co, rtol=0, atol=COHP_TOL)
+    # the recompute workflow keeps no pattern rows: a clear state error
+    ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow="recompute")
+    from paper_1210_1531_amd import MagError
+    with pytest.raises(MagError):
+        ctx.cohp(e, eta)
+
+
 def test_icohp_sum_rule_at_full_size():
     # the benchmark cell: Eq. 6 and Eq. 8 on every block
     from paper_1210_1531_amd import model

@@ -1,7 +1,9 @@
 """Pins of the oracle's crystal orbital Hamiltonian populations (Eqs. 4-8):
 the sigma/pi split of the two-center blocks against the textbook forms, the
 sum rule of Eq. 6, the decomposition of Eq. 8, pair symmetry in the exact
-regime, and the sign of the bond populations in perfect diamond."""
+regime, the sign of the bond populations in perfect diamond, and the
+energy-resolved COHP against the Galerkin column of the Krylov code and, in
+the exact regime, against the dense resolvent (zS - H)^-1 of Eq. 1."""
 import numpy as np
 import pytest
 
@@ -99,3 +101,53 @@ def test_bonds_of_perfect_diamond():
     nnn = np.abs(dist - np.sqrt(2) / 2 * 3.567) < 1e-6
     if nnn.any():
         np.testing.assert_allclose(B[nnn], B[nnn][0], rtol=0, atol=1e-10)
+
+
+def test_cohp_against_galerkin_columns(cfg1):
+    # the block-wise COHP against G taken column by column from the Krylov
+    # code's own Galerkin column (a different indexing route: cluster rows of
+    # the column atom instead of pattern rows)
+    from oracle import krylov
+    sysm, r = cfg1
+    e = np.array([-8.0, -3.0, 0.5, 4.0])
+    eta = 0.05
+    C = solve.cohp(sysm, r.cd, e, eta)
+    assert C.shape == (sum(len(k) for k in sysm.rows), e.size)
+    atoms = neighbors.cluster_of(sysm.pos, sysm.cell, 0, sysm.r_cluster)
+    Hc, Sc = neighbors.cluster_matrices(sysm.pos, sysm.cell, atoms, sysm.params)
+    H = sysm.H.toarray()
+    b = 0
+    for J in range(3):
+        for t, K in enumerate(sysm.rows[J]):
+            ref = np.zeros(e.size)
+            for a in range(4):
+                res = krylov.column_mode_k(Hc, Sc, 4 * int(np.searchsorted(atoms, J)) + a, sysm.nu)
+                G = krylov.green_column(res, e + 1j * eta)
+                kl = int(np.searchsorted(atoms, K))
+                for c in range(4):
+                    ref += -(krylov.G_SPIN / np.pi) * H[4 * J + a, 4 * K + c] * G[4 * kl + c].imag
+            np.testing.assert_allclose(C[b], ref, rtol=1e-11, atol=1e-11)
+            b += 1
+
+
+def test_cohp_exact_regime_equals_resolvent():
+    # nu = M on the whole cell: the Galerkin G is (zS - H)^-1 itself (Eq. 1)
+    s = gen.make_structure(cells=(2, 2, 2), vacancy_frac=0.5, sigma=0.05, seed=4242,
+                           nu=128, r_cluster=0.0)
+    sysm = solve.build_system(s)
+    cd = solve.column_data(sysm, workers=8)
+    e = np.array([-6.0, 1.0])
+    eta = 0.1
+    C = solve.cohp(sysm, cd, e, eta)
+    H, S = sysm.H.toarray(), sysm.S.toarray()
+    ref = []
+    Gs = [np.linalg.solve(z * S - H, np.eye(H.shape[0])) for z in e + 1j * eta]
+    for J in range(sysm.n_atoms):
+        for K in sysm.rows[J]:
+            row = []
+            for G in Gs:
+                blk = G[4 * int(K):4 * int(K) + 4, 4 * J:4 * J + 4]  # G_{Kb;Ja}
+                hb = H[4 * J:4 * J + 4, 4 * int(K):4 * int(K) + 4]  # H_{Ja;Kb}
+                row.append(-(2.0 / np.pi) * np.sum(hb * blk.T).imag)
+            ref.append(row)
+    np.testing.assert_allclose(C, np.array(ref), rtol=0, atol=1e-9)
