@@ -202,7 +202,7 @@ def test_sampled_columns_at_full_size_config2():
     assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
 
 
-@pytest.mark.parametrize("nu", [20, 30, 40])
+@pytest.mark.parametrize("nu", [12, 20, 30, 40, 48])
 def test_sampled_columns_at_full_size_void_cell(nu):
     # the 16x16x16 void cell: clusters from 61 to 164 atoms, so several
     # workgroup shapes run in one pass (two rows per thread at nu = 40); a
