@@ -183,3 +183,10 @@ def make(k, nu=None, seed=None) -> Structure:
         s.nu = int(nu)
     s.meta["config"] = k
     return s
+
+
+def random_velocities(n_atoms: int, sigma: float, seed: int) -> np.ndarray:
+    """(n_atoms, 3) normal velocity components of standard deviation sigma with
+    the mean removed (zero total momentum for equal masses)."""
+    v = np.random.default_rng(seed).normal(0.0, sigma, size=(n_atoms, 3))
+    return v - v.mean(axis=0, keepdims=True)
