@@ -42,6 +42,8 @@ def parse(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-column-launch baseline")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--md-steps", type=int, default=4,
+                    help="MD steps timed after the solve benchmark (0: none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 512 MiB fill and device copy (HBM counter calibration)")
     return ap.parse_args(argv)
@@ -304,6 +306,22 @@ def main(argv=None):
         terms = nblk * grid.size * 4 * s.nu
         out["cohp"] = {"ms": t_co, "blocks": nblk, "energies": int(grid.size),
                        "G_terms_per_s": terms / (t_co * 1e-3) / 1e9}
+    # MD steps: velocity Verlet at 300 K, each step rebuilding H, S, pattern
+    # and clusters, solving every column and taking the forces plus the pair
+    # repulsion (one warm-up step first)
+    if args.md_steps > 0:
+        vel = torch.tensor(gen.random_velocities(s.n_atoms, model.thermal_sigma(300.0), 1),
+                           dtype=torch.float64, device="cuda")
+        md_kw = dict(r_cluster=s.r_cluster, **model.PAIR_REPULSION, **opts)
+        ctx.md_run(sk, pos, vel, s.cell, 0.5, model.MASS_CARBON, 1, **md_kw)
+        _, _, _, th = ctx.md_run(sk, pos, vel, s.cell, 0.5, model.MASS_CARBON, args.md_steps,
+                                 **md_kw)
+        t_md = ctx.stats()["t_md_step_ms"]
+        e_tot = th[:, 0] + th[:, 1]
+        out["md"] = {"ms_per_step": t_md, "steps": args.md_steps, "dt_fs": 0.5,
+                     "columns_per_s": M / (t_md * 1e-3),
+                     "E_tot_change_per_atom": float(e_tot[-1] - e_tot[0]) / s.n_atoms,
+                     "step": "rebuild H, S, pattern, clusters + fwd + bwd + forces + pair term"}
     if args.copy_probe:
         a = torch.full((64 * 1024 * 1024,), 1.0, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

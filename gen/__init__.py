@@ -2,7 +2,8 @@
 
 This package produces atomic structures (positions in an orthorhombic periodic
 box) and the run settings that go with them.  It holds none of the electronic
-structure arithmetic: no Hamiltonian, no clusters, no Krylov steps.  Both the
+structure arithmetic: no Hamiltonian, no clusters, no Krylov steps.  Seeded
+initial velocities for MD runs come from here too.  Both the
 GPU library's tests and the CPU oracle draw their inputs from here.
 """
 from .structures import (  # noqa: F401
@@ -12,4 +13,5 @@ from .structures import (  # noqa: F401
     make,
     CONFIGS,
     config_seed,
+    random_velocities,
 )

@@ -319,6 +319,52 @@ int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigm
 int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C, int mem_kind);
 
 /* ---------------------------------------------------------------------- */
+/* MD step                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Pair repulsion of the tight-binding total energy on the pattern of the
+ * last mag_sk_build (its positions, box and model):
+ *   E_rep = sum over atom pairs {I, K} closer than r_cut of
+ *           phi(r) = phi0 (r0 / r)^m_rep fc(r),
+ * r0 and the smooth cutoff fc (r_on .. r_cut) being the SK model's.  This is
+ * the repulsive part that a tight-binding total energy adds to the band
+ * energy (the form of Goodwin, Skinner and Pettifor for (r0/r)^2 hoppings).
+ * Outputs: *E_rep (host; may be NULL), e_atom (n_atoms: the half of each of
+ * an atom's pairs; may be NULL), F (n_atoms x 3: -dE_rep/dR; may be NULL).
+ * Errors: MAG_ESTATE without a build; MAG_EINVAL for non-finite phi0 or
+ * m_rep <= 0. */
+int mag_pair_repulsion(mag_ctx* ctx, double phi0, double m_rep, double* E_rep, double* e_atom,
+                       double* F, int mem_kind);
+
+typedef struct {
+  double dt;        /* time step, fs (> 0) */
+  double mass;      /* mass of every atom, amu (> 0) */
+  double phi0;      /* pair repulsion prefactor, eV (0: band energy only) */
+  double m_rep;     /* pair repulsion exponent (> 0 when phi0 != 0) */
+  double r_cluster; /* cluster radius of every column, Angstrom (<= 0: the whole cell) */
+  int n_steps;      /* MD steps (>= 0) */
+} mag_md_opts;
+
+/* n_steps of velocity Verlet on the potential energy E_pot = A_free + E_rep,
+ * each step being the method's unit of work: H and S rebuilt from the model
+ * at the new positions (pattern and clusters included), the columns solved
+ * with `opts`, the forces taken through the density matrix (mag_forces) plus
+ * the pair term, and
+ *   v += dt F / (2 m);  x += dt v (wrapped into [0, L));  F = F(x);  v += dt F / (2 m)
+ * in units of Angstrom, fs, eV and amu (1 amu A^2/fs^2 = 103.6427 eV).
+ * pos and vel (n_atoms x 3, mem_kind) hold the start on entry and the end on
+ * return; F (n_atoms x 3, mem_kind; may be NULL) receives the last forces;
+ * thermo (host, (n_steps + 1) x 5) receives per frame, the start first:
+ * E_pot, E_kin = sum m |v|^2 / 2, mu, E_band, E_rep (eV).  The context holds
+ * the last frame's system and solve afterwards (mag_energy, mag_icohp ...).
+ * Errors: as mag_sk_build, mag_set_system and mag_solve_columns, for the
+ * frame at which they occur (pos and vel then hold that frame); MAG_EINVAL
+ * for bad md options or NULL arrays. */
+int mag_md_run(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opts,
+               const mag_md_opts* md, int64_t n_atoms, const double cell[3], double* pos,
+               double* vel, double* F, double* thermo, int mem_kind);
+
+/* ---------------------------------------------------------------------- */
 /* diagnostics                                                              */
 /* ---------------------------------------------------------------------- */
 
@@ -344,6 +390,7 @@ typedef struct {
   double autotune_ms;      /* time spent timing launch plans (first use of a shape) */
   double t_icohp_ms;       /* last mag_icohp (after pass 2) */
   double t_cohp_ms;        /* last mag_cohp */
+  double t_md_step_ms;     /* last mag_md_run: average wall time of one step */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

@@ -73,6 +73,17 @@ class MagOpts(C.Structure):
     ]
 
 
+class MagMDOpts(C.Structure):
+    _fields_ = [
+        ("dt", C.c_double),
+        ("mass", C.c_double),
+        ("phi0", C.c_double),
+        ("m_rep", C.c_double),
+        ("r_cluster", C.c_double),
+        ("n_steps", C.c_int),
+    ]
+
+
 class MagStats(C.Structure):
     _fields_ = [
         ("t_set_system_ms", C.c_double),
@@ -95,6 +106,7 @@ class MagStats(C.Structure):
         ("autotune_ms", C.c_double),
         ("t_icohp_ms", C.c_double),
         ("t_cohp_ms", C.c_double),
+        ("t_md_step_ms", C.c_double),
     ]
 
 
@@ -129,6 +141,9 @@ PROTOTYPES = {
     "mag_forces": (I, [CTX, C.POINTER(MagSKModel), P, I]),
     "mag_icohp": (I, [CTX, C.POINTER(MagSKModel), P, P, P, I]),
     "mag_cohp": (I, [CTX, C.POINTER(D), I, D, P, I]),
+    "mag_pair_repulsion": (I, [CTX, D, D, C.POINTER(D), P, P, I]),
+    "mag_md_run": (I, [CTX, C.POINTER(MagSKModel), C.POINTER(MagOpts), C.POINTER(MagMDOpts), I64,
+                       C.POINTER(D), P, P, P, C.POINTER(D), I]),
     "mag_get_stats": (I, [CTX, C.POINTER(MagStats)]),
 }
 

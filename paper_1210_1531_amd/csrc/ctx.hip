@@ -2,6 +2,7 @@
 // the two Green's-function passes of the memory-saving workflow (Eq. 3), the
 // chemical potential, energies, derivatives and forces.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <numeric>
 
@@ -1699,6 +1700,152 @@ int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C
   return take_errors(ctx, "mag_cohp");
 }
 
+// E_rep (device scalar in md_sum[0]), e_atom (md_e) and F_rep (md_Frep) on
+// the last build's pattern
+static int pair_terms(mag_ctx* ctx, double phi0, double m_rep) {
+  const int64_t n = ctx->sk_n;
+  ALLOC(ctx->md_e, sizeof(double) * n);
+  ALLOC(ctx->md_Frep, sizeof(double) * 3 * n);
+  ALLOC(ctx->md_sum, sizeof(double) * 2);
+  HIPCHK(launch_pair_rep(ctx->sk_model, ctx->sk_pos.as<double>(), n, ctx->sk_cell,
+                         ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), phi0, m_rep,
+                         ctx->md_e.as<double>(), ctx->md_Frep.as<double>(), ctx->stream));
+  HIPCHK(launch_sum(ctx->md_e.as<double>(), n, 0, ctx->md_sum.as<double>(), ctx->stream));
+  return MAG_OK;
+}
+
+int mag_pair_repulsion(mag_ctx* ctx, double phi0, double m_rep, double* E_rep, double* e_atom,
+                       double* F, int mem_kind) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!ctx->sk_built) return fail(ctx, MAG_ESTATE, "no Slater-Koster build");
+  if (!std::isfinite(phi0) || !std::isfinite(m_rep) || !(m_rep > 0.0))
+    return fail(ctx, MAG_EINVAL, "need finite phi0 and m_rep > 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  TRY(pair_terms(ctx, phi0, m_rep));
+  const int64_t n = ctx->sk_n;
+  if (e_atom) TRY(copy_out(ctx, e_atom, ctx->md_e.p, sizeof(double) * n, mem_kind));
+  if (F) TRY(copy_out(ctx, F, ctx->md_Frep.p, sizeof(double) * 3 * n, mem_kind));
+  double e = 0.0;
+  HIPCHK(hipMemcpyAsync(&e, ctx->md_sum.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
+  if (E_rep) *E_rep = e;
+  return MAG_OK;
+}
+
+// one frame of the MD run: build, system, solve, forces (into md_F) and the
+// frame's energies; the kinetic energy is taken by the caller
+static int md_frame(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opts,
+                    const mag_md_opts* md, int64_t n, const double cell[3], double* th) {
+  int64_t nnz = 0;
+  TRY(mag_sk_build(ctx, model, n, ctx->md_x.as<double>(), cell, MAG_DEVICE, &nnz));
+  mag_system sys{};
+  sys.n_atoms = n;
+  sys.nnz = nnz;
+  sys.rowptr = ctx->sk_rowptr.as<int64_t>();
+  sys.colind = ctx->sk_colind.as<int32_t>();
+  sys.H = ctx->sk_H.as<double>();
+  sys.S = ctx->sk_S.as<double>();
+  sys.pos = ctx->md_x.as<double>();
+  for (int d = 0; d < 3; ++d) sys.cell[d] = cell[d];
+  sys.r_cluster = md->r_cluster;
+  TRY(mag_set_system(ctx, &sys, MAG_DEVICE));
+  double mu = 0.0, E = 0.0, A = 0.0;
+  TRY(mag_solve_columns(ctx, opts, &mu, &E, &A));
+  TRY(mag_forces(ctx, model, ctx->md_F.as<double>(), MAG_DEVICE));
+  double Erep = 0.0;
+  if (md->phi0 != 0.0) {
+    TRY(pair_terms(ctx, md->phi0, md->m_rep));
+    HIPCHK(launch_axpy(ctx->md_F.as<double>(), ctx->md_Frep.as<double>(), 3 * n, 1.0,
+                       ctx->stream));
+    HIPCHK(hipMemcpyAsync(&Erep, ctx->md_sum.p, sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    TRY(sync(ctx));
+  }
+  th[0] = A + Erep;
+  th[2] = mu;
+  th[3] = E;
+  th[4] = Erep;
+  return take_errors(ctx, "mag_md_run");
+}
+
+static int md_kinetic(mag_ctx* ctx, const mag_md_opts* md, int64_t n, double* th) {
+  ALLOC(ctx->md_sum, sizeof(double) * 2);
+  HIPCHK(launch_sum(ctx->md_v.as<double>(), 3 * n, 1, ctx->md_sum.as<double>() + 1, ctx->stream));
+  double vv = 0.0;
+  HIPCHK(hipMemcpyAsync(&vv, ctx->md_sum.as<double>() + 1, sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  TRY(sync(ctx));
+  th[1] = 0.5 * md->mass * vv * AMU_A2_FS2_EV;
+  return MAG_OK;
+}
+
+int mag_md_run(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opts,
+               const mag_md_opts* md, int64_t n_atoms, const double cell[3], double* pos,
+               double* vel, double* F, double* thermo, int mem_kind) {
+  if (!ctx) return MAG_EINVAL;
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!model_ok(model)) return fail(ctx, MAG_EINVAL, "invalid Slater-Koster model");
+  if (!opts || !md || !cell || !pos || !vel || !thermo)
+    return fail(ctx, MAG_EINVAL, "NULL argument");
+  if (n_atoms < 1) return fail(ctx, MAG_EINVAL, "need n_atoms >= 1");
+  if (!(md->dt > 0.0) || !std::isfinite(md->dt) || !(md->mass > 0.0) ||
+      !std::isfinite(md->mass) || md->n_steps < 0 || !std::isfinite(md->phi0) ||
+      !std::isfinite(md->r_cluster) || (md->phi0 != 0.0 && !(md->m_rep > 0.0)) ||
+      !std::isfinite(md->m_rep))
+    return fail(ctx, MAG_EINVAL, "need dt > 0, mass > 0, n_steps >= 0, finite phi0 and m_rep > 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t n = n_atoms;
+  ALLOC(ctx->md_x, sizeof(double) * 3 * n);
+  ALLOC(ctx->md_v, sizeof(double) * 3 * n);
+  ALLOC(ctx->md_F, sizeof(double) * 3 * n);
+  HIPCHK(hipMemcpyAsync(ctx->md_x.p, pos, sizeof(double) * 3 * n, kind_in(mem_kind), ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->md_v.p, vel, sizeof(double) * 3 * n, kind_in(mem_kind), ctx->stream));
+  HIPCHK(launch_check_finite(ctx->md_v.as<double>(), 3 * n, ctx->errflag.as<int32_t>(),
+                             ctx->stream));
+  TRY(take_errors(ctx, "mag_md_run"));
+  // state back to the caller, also when a frame fails
+  auto give_back = [&]() -> int {
+    TRY(copy_out(ctx, pos, ctx->md_x.p, sizeof(double) * 3 * n, mem_kind));
+    TRY(copy_out(ctx, vel, ctx->md_v.p, sizeof(double) * 3 * n, mem_kind));
+    if (F) TRY(copy_out(ctx, F, ctx->md_F.p, sizeof(double) * 3 * n, mem_kind));
+    return sync(ctx);
+  };
+  int rc = md_frame(ctx, model, opts, md, n, cell, thermo);
+  if (rc == MAG_OK) rc = md_kinetic(ctx, md, n, thermo);
+  if (rc != MAG_OK) {
+    (void)give_back();
+    return rc;
+  }
+  const double c = 0.5 * md->dt / (md->mass * AMU_A2_FS2_EV);
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int step = 1; step <= md->n_steps; ++step) {
+    double* th = thermo + 5 * (int64_t)step;
+    rc = (launch_md_kick(ctx->md_v.as<double>(), ctx->md_F.as<double>(), 3 * n, c, ctx->stream) ==
+          hipSuccess)
+             ? MAG_OK
+             : fail(ctx, MAG_EHIP, "MD kick launch failed");
+    if (rc == MAG_OK &&
+        launch_md_drift(ctx->md_x.as<double>(), ctx->md_v.as<double>(), n, md->dt, cell,
+                        ctx->stream) != hipSuccess)
+      rc = fail(ctx, MAG_EHIP, "MD drift launch failed");
+    if (rc == MAG_OK) rc = md_frame(ctx, model, opts, md, n, cell, th);
+    if (rc == MAG_OK &&
+        launch_md_kick(ctx->md_v.as<double>(), ctx->md_F.as<double>(), 3 * n, c, ctx->stream) !=
+            hipSuccess)
+      rc = fail(ctx, MAG_EHIP, "MD kick launch failed");
+    if (rc == MAG_OK) rc = md_kinetic(ctx, md, n, th);
+    if (rc != MAG_OK) {
+      (void)give_back();
+      return rc;
+    }
+  }
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ctx->stats.t_md_step_ms = md->n_steps > 0 ? ms / md->n_steps : 0.0;
+  return give_back();
+}
+
 int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
   if (!ctx || !out) return MAG_EINVAL;
   int64_t bytes = 0;
@@ -1710,7 +1857,9 @@ int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
                           &ctx->k_urow, &ctx->k_qpat, &ctx->k_nu, &ctx->k_npat, &ctx->k_cols,
                           &ctx->k_queue, &ctx->errflag, &ctx->tmp_cols, &ctx->tmp_off,
                           &ctx->tmp_out, &ctx->k_trid, &ctx->k_evu, &ctx->k_rot,
-                          &ctx->k_sweep, &ctx->k_qlst, &ctx->k_fbl, &ctx->k_fbc};
+                          &ctx->k_sweep, &ctx->k_qlst, &ctx->k_fbl, &ctx->k_fbc,
+                          &ctx->md_x, &ctx->md_v, &ctx->md_F, &ctx->md_Frep, &ctx->md_e,
+                          &ctx->md_sum};
   for (const DevBuf* b : bufs) bytes += (int64_t)b->bytes;
   ctx->stats.device_bytes = bytes;
   *out = ctx->stats;

@@ -232,6 +232,16 @@ hipError_t launch_icohp(const SKModelDev& m, const double* pos, int64_t n, int64
                         const double cell[3], const int32_t* bptr, const int32_t* bcol,
                         const double* bval, const double* rho, double* B, double* Bsig,
                         double* Bpi, hipStream_t s);
+hipError_t launch_pair_rep(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
+                           const int32_t* bptr, const int32_t* bcol, double phi0, double mexp,
+                           double* e, double* F, hipStream_t s);
+// MD step helpers (md.hip)
+hipError_t launch_md_kick(double* v, const double* F, int64_t n3, double c, hipStream_t s);
+hipError_t launch_md_drift(double* x, const double* v, int64_t n, double dt, const double cell[3],
+                           hipStream_t s);
+hipError_t launch_axpy(double* y, const double* x, int64_t n, double a, hipStream_t s);
+hipError_t launch_sum(const double* a, int64_t n, int squares, double* out, hipStream_t s);
+extern const double AMU_A2_FS2_EV;
 hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
                          const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
                          const double* gH, const double* gS, double sign_gS, double* grad,
@@ -276,6 +286,7 @@ struct mag_ctx {
   double sk_cell[3] = {0, 0, 0};
   mag::SKModelDev sk_model{};
   mag::DevBuf sk_pos, sk_bptr, sk_bcol, sk_rowptr, sk_colind, sk_H, sk_S;
+  mag::DevBuf md_x, md_v, md_F, md_Frep, md_e, md_sum;  // MD step state
 
   // system
   bool has_system = false;

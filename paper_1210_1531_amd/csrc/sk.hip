@@ -198,10 +198,11 @@ __global__ void sk_csr_kernel(const int32_t* bptr, const int32_t* bcol, int64_t 
 // ---------------------------------------------------------------------------
 // two-center blocks and their derivatives
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void radial(const SKModelDev& m, double r, double& u, double& du) {
+// quintic smooth step from 1 at r_on to 0 at r_cut, and its derivative
+__device__ __forceinline__ void smooth_cutoff(const SKModelDev& m, double r, double& fc,
+                                              double& dfc) {
   const double width = m.r_cut - m.r_on;
   const double t = (r - m.r_on) / width;
-  double fc, dfc;
   if (t <= 0.0) {
     fc = 1.0;
     dfc = 0.0;
@@ -213,6 +214,11 @@ __device__ __forceinline__ void radial(const SKModelDev& m, double r, double& u,
     fc = 1.0 - (10.0 * t3 - 15.0 * t3 * t + 6.0 * t3 * t2);
     dfc = -(30.0 * t2 - 60.0 * t3 + 30.0 * t3 * t) / width;
   }
+}
+
+__device__ __forceinline__ void radial(const SKModelDev& m, double r, double& u, double& du) {
+  double fc, dfc;
+  smooth_cutoff(m, r, fc, dfc);
   const double g = (m.r0 / r) * (m.r0 / r);
   const double dg = -2.0 * m.r0 * m.r0 / (r * r * r);
   u = g * fc;
@@ -422,6 +428,50 @@ __global__ void sk_vjp_kernel(SKModelDev m, const double* pos, int64_t n, Box bo
     }
   }
   for (int c = 0; c < 3; ++c) grad[3 * I + c] = acc[c];
+}
+
+// Pair repulsion of the total energy: phi(r) = phi0 (r0 / r)^m fc(r) over
+// the atom pairs of the pattern (one thread per atom J, its block row).  Both
+// ends of a pair see it, so e[J] takes half of each phi; the force on J is
+// sum_K phi'(r) d / r with d = R_K - R_J.
+__global__ void pair_rep_kernel(SKModelDev m, const double* pos, int64_t n, Box box,
+                                const int32_t* bptr, const int32_t* bcol, double phi0,
+                                double mexp, double* e, double* F) {
+  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (J >= n) return;
+  double eJ = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int64_t b = bptr[J]; b < bptr[J + 1]; ++b) {
+    const int K = bcol[b];
+    if (K == J) continue;
+    double dx = pos[3 * K] - pos[3 * J], dy = pos[3 * K + 1] - pos[3 * J + 1],
+           dz = pos[3 * K + 2] - pos[3 * J + 2];
+    min_image(box, dx, dy, dz);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(r < m.r_cut)) continue;
+    double fc, dfc;
+    smooth_cutoff(m, r, fc, dfc);
+    const double g = phi0 * pow(m.r0 / r, mexp);
+    const double dphi = (-mexp * g / r) * fc + g * dfc;
+    eJ += 0.5 * (g * fc);
+    const double c = dphi / r;
+    fx += c * dx;
+    fy += c * dy;
+    fz += c * dz;
+  }
+  e[J] = eJ;
+  F[3 * J] = fx;
+  F[3 * J + 1] = fy;
+  F[3 * J + 2] = fz;
+}
+
+hipError_t launch_pair_rep(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
+                           const int32_t* bptr, const int32_t* bcol, double phi0, double mexp,
+                           double* e, double* F, hipStream_t s) {
+  Box box{{cell[0], cell[1], cell[2]}};
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_rep_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, m, pos, n, box,
+                     bptr, bcol, phi0, mexp, e, F);
+  return hipGetLastError();
 }
 
 hipError_t launch_sk_count(const double* pos, int64_t n, const double cell[3], double rc,

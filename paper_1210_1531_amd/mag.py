@@ -300,6 +300,45 @@ class Context:
                                        float(eta), ptrs[0], kind))
         return outs[0]
 
+    # -------------------------------------------------------------- MD step
+    def pair_repulsion(self, phi0, m_rep):
+        """(E_rep, e_atom, F_rep) of the pair term on the last sk_build
+        (see mag_pair_repulsion)."""
+        outs, ptrs, kind = self._outputs([((self.sk_n,), np.float64), ((self.sk_n, 3), np.float64)])
+        e = C.c_double()
+        self._check(self._lib.mag_pair_repulsion(self._h, float(phi0), float(m_rep), C.byref(e),
+                                                 ptrs[0], ptrs[1], kind))
+        return e.value, outs[0], outs[1]
+
+    def md_run(self, model, pos, vel, cell, dt, mass, n_steps, phi0=0.0, m_rep=4.0,
+               r_cluster=0.0, **kw):
+        """n_steps of velocity Verlet (see mag_md_run).  Returns (pos, vel, F,
+        thermo) at the end; thermo[k] = (E_pot, E_kin, mu, E_band, E_rep) of
+        frame k (frame 0: the start)."""
+        o = make_opts(**kw)
+        md = L.MagMDOpts(dt=float(dt), mass=float(mass), phi0=float(phi0), m_rep=float(m_rep),
+                         r_cluster=float(r_cluster), n_steps=int(n_steps))
+        n = int(pos.shape[0])
+        outs, ptrs, kind = self._outputs([((n, 3), np.float64)] * 3)
+        for dst, src in zip(outs[:2], (pos, vel)):
+            if self.device_outputs:
+                dst.copy_(src if _is_dev(src) else torch.as_tensor(np.asarray(src, np.float64)))
+            else:
+                np.copyto(dst, src.detach().cpu().numpy() if _is_dev(src) else np.asarray(src))
+        cellv = (C.c_double * 3)(*[float(x) for x in cell])
+        thermo = np.zeros((int(n_steps) + 1, 5), dtype=np.float64)
+        self._check(self._lib.mag_md_run(self._h, C.byref(model), C.byref(o), C.byref(md), n, cellv,
+                                         ptrs[0], ptrs[1], ptrs[2],
+                                         thermo.ctypes.data_as(C.POINTER(C.c_double)), kind))
+        # the context now holds the last frame's build, system and solve
+        rowptr = np.empty(4 * n + 1, dtype=np.int64)
+        self._check(self._lib.mag_sk_get_csr(self._h, C.c_void_p(rowptr.ctypes.data), None, None,
+                                             None, L.MAG_HOST))
+        self.sk_n = self.n_atoms = n
+        self.sk_nnz = self.nnz = int(rowptr[-1])
+        self.opts = o
+        return outs[0], outs[1], outs[2], thermo
+
     def stats(self):
         s = L.MagStats()
         self._check(self._lib.mag_get_stats(self._h, C.byref(s)))

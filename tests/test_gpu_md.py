@@ -1,0 +1,126 @@
+"""GPU MD step against the oracle: the pair repulsion and whole velocity Verlet
+frames (rebuild, solve, forces, kick and drift), on seeded cells.
+
+Bars: pair energies and forces to rounding (1e-11 eV, eV/A); frames of the
+MD run within the force bar |dF| <= 1e-8 eV/A and |dE|/atom <= 1e-9 eV, which
+move positions and velocities by at most dt^2 |dF| / m (1e-12 A) per step.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gen import structures as gs
+from gpu_helpers import log, np_, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+MASS = 12.011  # amu
+KB = 8.617333262e-5  # eV / K
+AMU_EV = 1.66053906660e-17 / 1.602176634e-19  # amu (A/fs)^2 in eV (CODATA 2018)
+PHI0, MREP = 13.18, 4.0
+PAIR_TOL = 1e-11
+F_TOL = 1e-8
+E_TOL = 1e-9
+
+
+def _sigma(T):
+    return float(np.sqrt(KB * T / (MASS * AMU_EV)))
+
+
+def _min_image(d, cell):
+    return d - cell * np.rint(d / cell)
+
+
+@pytest.mark.parametrize("key", ["mini_vac", 2])
+def test_pair_repulsion_matches_oracle(key):
+    torch = torch_cuda()
+    from oracle import md
+    from paper_1210_1531_amd import Context, model
+    s = gs.make(key)
+    log(f"[pair {key}] {s.n_atoms} atoms")
+    ctx = Context()
+    ctx.sk_build(model.sk_model(), torch.tensor(s.pos, dtype=torch.float64, device="cuda"), s.cell)
+    E, e, F = ctx.pair_repulsion(PHI0, MREP)
+    e, F = np_(e), np_(F)
+    atoms = None if key == "mini_vac" else np.sort(
+        np.random.default_rng(5).choice(s.n_atoms, 96, replace=False))
+    Eo, eo, Fo = md.pair_repulsion(s.pos, s.cell, PHI0, MREP, atoms=atoms)
+    rows = slice(None) if atoms is None else atoms
+    de, dF = np.abs(e[rows] - eo).max(), np.abs(F[rows] - Fo).max()
+    log(f"[pair {key}] E_rep {E:.10f}, max |de| {de:.3e}, max |dF| {dF:.3e}")
+    assert de <= PAIR_TOL and dF <= PAIR_TOL
+    if Eo is not None:
+        assert abs(E - Eo) <= 1e-12 * abs(Eo)
+    assert abs(E - e.sum()) <= 1e-12 * abs(E)
+    assert np.abs(F.sum(axis=0)).max() < 1e-9  # the pair forces cancel
+
+
+def test_md_frames_match_oracle_mini_vac():
+    torch = torch_cuda()
+    from oracle import md
+    from paper_1210_1531_amd import Context, model
+    s = gs.make("mini_vac")
+    v0 = gs.random_velocities(s.n_atoms, _sigma(300.0), 21)
+    dt, steps = 0.5, 2
+    log(f"[md mini_vac] {s.n_atoms} atoms, {steps} steps of {dt} fs")
+    ctx = Context()
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    pos, vel, F, th = ctx.md_run(model.sk_model(), dev(s.pos), dev(v0), s.cell, dt, MASS, steps,
+                                 phi0=PHI0, m_rep=MREP, r_cluster=s.r_cluster, nu=s.nu,
+                                 kT=s.kT, n_electrons=s.n_electrons)
+    pos, vel, F = np_(pos), np_(vel), np_(F)
+    workers = min(16, os.cpu_count() or 1)
+    fr = md.velocity_verlet(s.pos, v0, s.cell, md.krylov_forces(s, workers=workers, phi0=PHI0),
+                            MASS, dt, steps)
+    n = s.n_atoms
+    dx = np.abs(_min_image(pos - fr[-1].pos, s.cell)).max()
+    dv = np.abs(vel - fr[-1].vel).max()
+    dF = np.abs(F - fr[-1].F).max()
+    log(f"[md mini_vac] max |dx| {dx:.3e} A, |dv| {dv:.3e} A/fs, |dF| {dF:.3e} eV/A; "
+        f"E_tot {th[0, 0] + th[0, 1]:.8f} -> {th[-1, 0] + th[-1, 1]:.8f}; "
+        f"{ctx.stats()['t_md_step_ms']:.1f} ms per step")
+    assert dF <= F_TOL
+    assert dx <= 1e-10 and dv <= 1e-11
+    for k, f in enumerate(fr):
+        assert abs(th[k, 0] - f.E_pot) / n <= E_TOL
+        assert abs(th[k, 1] - f.E_kin) <= 1e-10 * f.E_kin
+        assert abs(th[k, 3] - f.E_band) / n <= E_TOL
+    # the context holds the last frame: its system and solve
+    assert ctx.n_atoms == n and abs(ctx.energy()["E_band"] - th[-1, 3]) <= 1e-12 * abs(th[-1, 3])
+
+
+def test_md_step_at_full_size_config2():
+    """One velocity Verlet step on the 3,892-atom cell: the step's algebra on
+    the GPU's own frame-0 forces, momentum, and a rerun from the same start."""
+    torch = torch_cuda()
+    from paper_1210_1531_amd import Context, model
+    s = gs.make(2)
+    v0 = gs.random_velocities(s.n_atoms, _sigma(300.0), 22)
+    dt = 0.5
+    ctx = Context()
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    kw = dict(phi0=PHI0, m_rep=MREP, r_cluster=s.r_cluster, nu=s.nu, kT=s.kT,
+              n_electrons=s.n_electrons)
+    log(f"[md config2] {s.n_atoms} atoms: frame 0")
+    _, _, F0, th0 = ctx.md_run(model.sk_model(), dev(s.pos), dev(v0), s.cell, dt, MASS, 0, **kw)
+    F0 = np_(F0)
+    log("[md config2] one step")
+    x1, v1, F1, th = ctx.md_run(model.sk_model(), dev(s.pos), dev(v0), s.cell, dt, MASS, 1, **kw)
+    x1, v1, F1 = np_(x1), np_(v1), np_(F1)
+    c = dt / (2 * MASS * AMU_EV)
+    x_exp = s.pos + dt * v0 + dt * c * F0
+    v_exp = v0 + c * (F0 + F1)
+    dx = np.abs(_min_image(x1 - x_exp, s.cell)).max()
+    dv = np.abs(v1 - v_exp).max()
+    log(f"[md config2] frame-0 rerun |dE| {abs(th[0, 0] - th0[0, 0]):.3e}, step |dx| {dx:.3e}, "
+        f"|dv| {dv:.3e}, E_tot {th[0, 0] + th[0, 1]:.6f} -> {th[1, 0] + th[1, 1]:.6f}, "
+        f"{ctx.stats()['t_md_step_ms']:.1f} ms per step")
+    assert np.array_equal(th[0], th0[0])  # deterministic solve: same start, same frame
+    # x is wrapped into the box, the expectation is not: compare minimum images
+    assert dx <= 1e-12 and dv <= 1e-12
+    assert np.all((x1 >= 0) & (x1 < s.cell[None, :]))
+    assert np.abs(F0.sum(axis=0)).max() < 1e-8 and np.abs(v1.sum(axis=0)).max() < 1e-11
+    # the step moves energy between kinetic and potential, not more than the
+    # Hellmann-Feynman reading at nu = 30 and the dt^2 error allow
+    assert abs((th[1, 0] + th[1, 1]) - (th[0, 0] + th[0, 1])) / s.n_atoms < 1e-3
