@@ -42,6 +42,8 @@ def parse(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-column-launch baseline")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--cocg-columns", type=int, default=2048,
+                    help="columns of the COCG sample (0: none)")
     ap.add_argument("--md-steps", type=int, default=4,
                     help="MD steps timed after the solve benchmark (0: none)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -306,6 +308,19 @@ def main(argv=None):
         terms = nblk * grid.size * 4 * s.nu
         out["cohp"] = {"ms": t_co, "blocks": nblk, "energies": int(grid.size),
                        "G_terms_per_s": terms / (t_co * 1e-3) / 1e9}
+    # COCG Green's-function columns (a second solver of Eq. 1) on a sample of
+    # columns at four energies, to tolerance 1e-10 (one pass over the
+    # cluster's blocks per step serves the four energies)
+    if args.cocg_columns > 0:
+        ncol = min(args.cocg_columns, M)
+        ccols = np.arange(0, M, max(1, M // ncol))[:ncol].astype(np.int32)
+        zc = np.array([-6.5 + 0.05j, -1.0 + 0.2j, 0.5 + 0.2j, 3.0 + 0.05j])
+        _, _, its = ctx.cocg_columns(ccols, zc, tol=1e-10, max_iter=4000)
+        t_cg = ctx.stats()["t_cocg_ms"]
+        out["cocg"] = {"ms": t_cg, "columns": int(ncol), "energies": int(zc.size),
+                       "steps_mean": float(np.mean(its)), "steps_max": int(np.max(its)),
+                       "converged": bool(np.all(its > 0)),
+                       "column_energies_per_s": ncol * zc.size / (t_cg * 1e-3)}
     # MD steps: velocity Verlet at 300 K, each step rebuilding H, S, pattern
     # and clusters, solving every column and taking the forces plus the pair
     # repulsion (one warm-up step first)

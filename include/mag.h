@@ -318,6 +318,25 @@ int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigm
  * any solve); MAG_EINVAL for ne <= 0, eta <= 0 or non-finite energies. */
 int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C, int mem_kind);
 
+/* Green's-function columns by a second solver of Eq. 1: the conjugate
+ * orthogonal conjugate gradient method (van der Vorst and Melissen), CG with
+ * the bilinear form u^T v for the complex symmetric A = z S - H.  Column
+ * cols[i] = (J, alpha) solves (z_q S_C - H_C) x = e_l on the cluster of atom
+ * J (the same locality as the multiple Arnoldi columns; the column of
+ * (z S - H)^-1 itself for a whole-cell cluster), from x = 0, until
+ * |r|_2 <= tol or max_iter steps, for nz energies z (re, im pairs, host;
+ * every Im z != 0).  Output layout as mag_green_columns: complex (re, im) at
+ * G_out[2 (offsets[i] * nz + q * len_i + c)]; offsets (n+1, int64, host) is
+ * filled by the call (G_out = NULL: offsets only).  iters (n x nz, int32,
+ * mem_kind; may be NULL) receives the steps taken, or -1 where tol was not
+ * reached or the method broke down (<p, A p> = 0 or <r, r> = 0); G_out then
+ * holds the last iterate.  Four energies share each pass over the cluster's
+ * H and S blocks.  Errors: MAG_EINVAL for bad columns, real or non-finite
+ * energies, tol <= 0 or max_iter < 1; MAG_ESTATE without a system. */
+int mag_cocg_columns(mag_ctx* ctx, const int32_t* cols, int64_t n, const double* z, int nz,
+                     double tol, int max_iter, double* G_out, int64_t* offsets,
+                     int32_t* iters, int mem_kind);
+
 /* ---------------------------------------------------------------------- */
 /* MD step                                                                  */
 /* ---------------------------------------------------------------------- */
@@ -391,6 +410,7 @@ typedef struct {
   double t_icohp_ms;       /* last mag_icohp (after pass 2) */
   double t_cohp_ms;        /* last mag_cohp */
   double t_md_step_ms;     /* last mag_md_run: average wall time of one step */
+  double t_cocg_ms;        /* last mag_cocg_columns (its kernels) */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

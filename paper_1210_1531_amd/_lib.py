@@ -107,6 +107,7 @@ class MagStats(C.Structure):
         ("t_icohp_ms", C.c_double),
         ("t_cohp_ms", C.c_double),
         ("t_md_step_ms", C.c_double),
+        ("t_cocg_ms", C.c_double),
     ]
 
 
@@ -141,6 +142,7 @@ PROTOTYPES = {
     "mag_forces": (I, [CTX, C.POINTER(MagSKModel), P, I]),
     "mag_icohp": (I, [CTX, C.POINTER(MagSKModel), P, P, P, I]),
     "mag_cohp": (I, [CTX, C.POINTER(D), I, D, P, I]),
+    "mag_cocg_columns": (I, [CTX, P, I64, P, I, D, I, P, P, P, I]),
     "mag_pair_repulsion": (I, [CTX, D, D, C.POINTER(D), P, P, I]),
     "mag_md_run": (I, [CTX, C.POINTER(MagSKModel), C.POINTER(MagOpts), C.POINTER(MagMDOpts), I64,
                        C.POINTER(D), P, P, P, C.POINTER(D), I]),

@@ -1582,6 +1582,68 @@ int mag_green_columns(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols, i
   return sync(ctx);
 }
 
+int mag_cocg_columns(mag_ctx* ctx, const int32_t* cols, int64_t n, const double* z, int nz,
+                     double tol, int max_iter, double* G_out, int64_t* offsets, int32_t* iters,
+                     int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (n < 0 || (n > 0 && !cols) || nz < 0 || (nz > 0 && !z))
+    return fail(ctx, MAG_EINVAL, "bad column or energy list");
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1)
+    return fail(ctx, MAG_EINVAL, "need tol > 0 and max_iter >= 1");
+  for (int q = 0; q < nz; ++q)
+    if (!std::isfinite(z[2 * q]) || !std::isfinite(z[2 * q + 1]) || z[2 * q + 1] == 0.0)
+      return fail(ctx, MAG_EINVAL, "energies must be finite with a nonzero imaginary part");
+  std::vector<int32_t> hcols;
+  TRY(upload_cols(ctx, cols, n, mem_kind, hcols));
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + NORB * ctx->h_clus_size[hcols[i] >> 2];
+  if (offsets) std::copy(off.begin(), off.end(), offsets);
+  if (!G_out || n == 0 || nz == 0) return MAG_OK;
+  Timer tm(ctx->stream);
+  DevBuf dcols, dz, doff, out, dit;
+  TRY(copy_in(ctx, dcols, hcols.data(), sizeof(int32_t) * n, MAG_HOST));
+  TRY(copy_in(ctx, dz, z, sizeof(double) * 2 * nz, MAG_HOST));
+  TRY(copy_in(ctx, doff, off.data(), sizeof(int64_t) * (n + 1), MAG_HOST));
+  double* dst = G_out;
+  if (mem_kind == MAG_HOST) {
+    ALLOC(out, sizeof(double) * 2 * std::max<int64_t>(off[n] * nz, 1));
+    dst = out.as<double>();
+  }
+  int32_t* pit = (mem_kind == MAG_DEVICE) ? iters : nullptr;
+  if (!pit) {
+    ALLOC(dit, sizeof(int32_t) * n * nz);
+    pit = dit.as<int32_t>();
+  }
+  CocgArgs ca{};
+  ca.cols = dcols.as<int32_t>();
+  ca.ncols = n;
+  ca.clus_ptr = ctx->clus_ptr.as<int64_t>();
+  ca.clus_atoms = ctx->clus_atoms.as<int32_t>();
+  ca.bptr = ctx->bptr.as<int32_t>();
+  ca.bcol = ctx->bcol.as<int32_t>();
+  ca.bval = ctx->bval.as<double>();
+  ca.z = dz.as<double>();
+  ca.nz = nz;
+  ca.tol = tol;
+  ca.max_iter = max_iter;
+  ca.off = doff.as<int64_t>();
+  ca.G = dst;
+  ca.iters = pit;
+  ca.err = ctx->errflag.as<int32_t>();
+  for (int q0 = 0; q0 < nz; q0 += COCG_NZ) {
+    ca.q0 = q0;
+    HIPCHK(launch_cocg(ca, ctx->stream));
+  }
+  TRY(take_errors(ctx, "mag_cocg_columns"));
+  ctx->stats.t_cocg_ms = tm.stop_ms();
+  if (mem_kind == MAG_HOST)
+    TRY(copy_out(ctx, G_out, dst, sizeof(double) * 2 * off[n] * nz, MAG_HOST));
+  if (iters && mem_kind == MAG_HOST)
+    TRY(copy_out(ctx, iters, pit, sizeof(int32_t) * n * nz, MAG_HOST));
+  return sync(ctx);
+}
+
 // ---------------------------------------------------------------------------
 // derivatives
 // ---------------------------------------------------------------------------

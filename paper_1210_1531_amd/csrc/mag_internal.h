@@ -235,6 +235,27 @@ hipError_t launch_icohp(const SKModelDev& m, const double* pos, int64_t n, int64
 hipError_t launch_pair_rep(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
                            const int32_t* bptr, const int32_t* bcol, double phi0, double mexp,
                            double* e, double* F, hipStream_t s);
+// COCG Green's-function columns (cocg.hip): energies per launch
+constexpr int COCG_NZ = 4;
+struct CocgArgs {
+  const int32_t* cols;  // global column ids
+  int64_t ncols;
+  const int64_t* clus_ptr;
+  const int32_t* clus_atoms;
+  const int32_t* bptr;
+  const int32_t* bcol;
+  const double* bval;  // block values, H then S per 4x4 block
+  const double* z;     // all energies (re, im)
+  int nz;              // number of energies
+  int q0;              // first energy of this launch
+  double tol;          // |r| <= tol (|b| = 1)
+  int max_iter;
+  const int64_t* off;  // output row offsets per column (n + 1)
+  double* G;           // complex out, G[2 (off[i] nz + q len_i + c)]
+  int32_t* iters;      // per column and energy: steps, or -1
+  int32_t* err;
+};
+hipError_t launch_cocg(const CocgArgs& a, hipStream_t s);
 // MD step helpers (md.hip)
 hipError_t launch_md_kick(double* v, const double* F, int64_t n3, double c, hipStream_t s);
 hipError_t launch_md_drift(double* x, const double* v, int64_t n, double dt, const double cell[3],

@@ -272,6 +272,28 @@ class Context:
                                                 C.c_void_p(off.ctypes.data), L.MAG_HOST))
         return out[0::2] + 1j * out[1::2], off
 
+    def cocg_columns(self, cols, z, tol=1e-10, max_iter=2000):
+        """Columns of (z S_C - H_C)^-1 by COCG on each column's cluster (see
+        mag_cocg_columns).  Returns (G, offsets, iters): G complex in the layout
+        of green_columns, iters (n, nz) steps taken or -1."""
+        cols = np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
+        zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=1).ravel())
+        n, nz = cols.size, z.size
+        off = np.zeros(n + 1, dtype=np.int64)
+        self._check(self._lib.mag_cocg_columns(self._h, C.c_void_p(cols.ctypes.data), n,
+                                               C.c_void_p(zz.ctypes.data), nz, float(tol),
+                                               int(max_iter), None, C.c_void_p(off.ctypes.data),
+                                               None, L.MAG_HOST))
+        out = np.empty(2 * int(off[-1]) * nz, dtype=np.float64)
+        iters = np.empty((n, nz), dtype=np.int32)
+        self._check(self._lib.mag_cocg_columns(self._h, C.c_void_p(cols.ctypes.data), n,
+                                               C.c_void_p(zz.ctypes.data), nz, float(tol),
+                                               int(max_iter), C.c_void_p(out.ctypes.data),
+                                               C.c_void_p(off.ctypes.data),
+                                               C.c_void_p(iters.ctypes.data), L.MAG_HOST))
+        return out[0::2] + 1j * out[1::2], off, iters
+
     def backward(self, gA=1.0):
         outs, ptrs, kind = self._outputs([((self.nnz,), np.float64), ((self.nnz,), np.float64)])
         self._check(self._lib.mag_backward(self._h, float(gA), ptrs[0], ptrs[1], kind))

@@ -73,6 +73,7 @@ def test_every_method_matches_the_prototypes(ctx, monkeypatch):
     ctx.forces(model.sk_model())
     ctx.icohp(model.sk_model())
     ctx.cohp([0.0, 1.0], 0.1)
+    ctx.cocg_columns([0, 1], [0.5 + 0.1j])
     ctx.pair_repulsion(13.18, 4.0)
     ctx.md_run(model.sk_model(), pos, np.zeros((4, 3)), cell, 0.5, 12.011, 2, phi0=13.18,
                r_cluster=6.0, nu=8, kT=0.1, n_electrons=16.0)

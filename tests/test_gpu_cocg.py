@@ -1,0 +1,103 @@
+"""GPU COCG Green's-function columns against the oracle.
+
+Converged columns are compared with dense solves of the cluster systems
+(z S_C - H_C) x = e_l, the definition of the result: with |r| <= tol and
+|A^-1| <= 1/|Im z| for the real symmetric pencil, |x - x*| <= tol / |Im z|.
+A fixed number of steps is compared iterate against iterate with the
+oracle's COCG (the same recurrences, summed in another order).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_context, log, oracle_system
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+Z = np.array([-14.0 + 0.3j, -6.5 + 0.05j, -1.0 + 1.0j, 0.5 + 0.2j, 3.0 + 0.05j, 9.0 + 0.5j])
+
+
+def _columns(G, off, nz, i):
+    n = off[i + 1] - off[i]
+    base = off[i] * nz
+    return [G[base + q * n: base + (q + 1) * n] for q in range(nz)]
+
+
+def _check_against_dense(key, cols, z):
+    from oracle import cocg
+    s, sysm = oracle_system(key)
+    ctx = gpu_context(s)
+    G, off, iters = ctx.cocg_columns(cols, z, tol=TOL, max_iter=4000)
+    D = cocg.green_columns_dense(sysm, cols, z)
+    worst = 0.0
+    for i in range(len(cols)):
+        got = _columns(G, off, z.size, i)
+        for q in range(z.size):
+            bound = TOL / abs(z[q].imag)
+            dev = np.abs(got[q] - D[i][q]).max()
+            worst = max(worst, dev / bound)
+            assert dev <= 2 * bound + 1e-13, (cols[i], z[q], dev)
+    log(f"[cocg {key}] {len(cols)} columns x {z.size} energies, steps {iters.min()}-{iters.max()}, "
+        f"worst |dx| / (tol/Im z) {worst:.3f}, {ctx.stats()['t_cocg_ms']:.2f} ms")
+    assert np.all(iters > 0)
+    return ctx, G, off, iters
+
+
+def test_cocg_matches_dense_cluster_solves_mini_vac():
+    s, _ = oracle_system("mini_vac")
+    cols = np.sort(np.random.default_rng(3).choice(4 * s.n_atoms, 24, replace=False))
+    _check_against_dense("mini_vac", cols, Z)
+
+
+def test_cocg_whole_cell_is_the_resolvent():
+    from oracle import solve
+    s, sysm = oracle_system(1)  # whole-cell cluster
+    ctx = gpu_context(s)
+    cols = np.array([0, 5, 130, 255])
+    z = Z[:4]
+    G, off, iters = ctx.cocg_columns(cols, z, tol=TOL, max_iter=4000)
+    for q, zq in enumerate(z):
+        ex = solve.green_exact(sysm, zq, cols)
+        for i in range(cols.size):
+            got = _columns(G, off, z.size, i)[q]
+            assert np.abs(got - ex[:, i]).max() <= 2 * TOL / abs(zq.imag)
+    assert np.all(iters > 0)
+
+
+def test_cocg_iterates_match_oracle_steps():
+    """Three and forty steps without convergence: every iterate entry equals
+    the oracle's COCG after the same steps, and the step count is -1."""
+    from oracle import cocg
+    s, sysm = oracle_system("mini_vac")
+    ctx = gpu_context(s)
+    cols = np.array([2, 77, 1201])
+    # the two sides sum in different orders, and the recurrence carries the
+    # rounding differences forward and grows them near the spectrum (Im z =
+    # 0.05): measured 3e-15 after 3 steps and 8e-11 after 40
+    for steps, bar in ((3, 1e-12), (40, 1e-9)):
+        G, off, iters = ctx.cocg_columns(cols, Z, tol=1e-30, max_iter=steps)
+        assert np.all(iters == -1)
+        ref, rit = cocg.green_columns_cocg(sysm, cols, Z, tol=1e-30, max_iter=steps)
+        assert np.all(rit == -1)
+        dev = max(np.abs(_columns(G, off, Z.size, i)[q] - ref[i][q]).max()
+                  for i in range(cols.size) for q in range(Z.size))
+        log(f"[cocg steps {steps}] max |d x_k| {dev:.3e}")
+        assert dev <= bar
+
+
+def test_cocg_sampled_columns_at_full_size_config2():
+    s, _ = oracle_system(2)
+    cols = np.sort(np.random.default_rng(9).choice(4 * s.n_atoms, 32, replace=False))
+    _check_against_dense(2, cols, Z[[1, 3, 5]])
+
+
+def test_cocg_errors():
+    from paper_1210_1531_amd import MagError
+    s, _ = oracle_system("mini_vac")
+    ctx = gpu_context(s)
+    with pytest.raises(MagError):
+        ctx.cocg_columns([0], [0.5 + 0.0j])  # real energy
+    with pytest.raises(MagError):
+        ctx.cocg_columns([0], [0.5 + 0.1j], tol=0.0)
+    with pytest.raises(MagError):
+        ctx.cocg_columns([4 * s.n_atoms], [0.5 + 0.1j])  # column out of range
