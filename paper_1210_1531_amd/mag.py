@@ -71,6 +71,7 @@ class Context:
         self._h = h
         self.n_atoms = 0
         self.nnz = 0
+        self.sk_n = 0
         self.sk_nnz = 0
         self.opts = None
 

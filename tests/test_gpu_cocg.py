@@ -49,6 +49,15 @@ def test_cocg_matches_dense_cluster_solves_mini_vac():
     _check_against_dense("mini_vac", cols, Z)
 
 
+def test_cocg_void_cell_mixed_cluster_sizes():
+    """Clusters of different sizes (atoms near voids) in one launch."""
+    s, _ = oracle_system("mini_void")
+    rng = np.random.default_rng(4)
+    cols = np.sort(rng.choice(4 * s.n_atoms, 20, replace=False))
+    ctx, G, off, iters = _check_against_dense("mini_void", cols, Z[[0, 2, 4]])
+    assert len(set(np.diff(off).tolist())) > 1  # the sample spans several cluster sizes
+
+
 def test_cocg_whole_cell_is_the_resolvent():
     from oracle import solve
     s, sysm = oracle_system(1)  # whole-cell cluster

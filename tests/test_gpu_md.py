@@ -124,3 +124,46 @@ def test_md_step_at_full_size_config2():
     # the step moves energy between kinetic and potential, not more than the
     # Hellmann-Feynman reading at nu = 30 and the dt^2 error allow
     assert abs((th[1, 0] + th[1, 1]) - (th[0, 0] + th[0, 1])) / s.n_atoms < 1e-3
+
+
+def test_md_whole_cell_cluster_matches_oracle():
+    """r_cluster <= 0: every column's cluster is the whole 64-atom cell."""
+    torch = torch_cuda()
+    from oracle import md
+    from paper_1210_1531_amd import Context, model
+    s = gs.make(1)
+    v0 = gs.random_velocities(s.n_atoms, _sigma(300.0), 23)
+    ctx = Context()
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    pos, vel, F, th = ctx.md_run(model.sk_model(), dev(s.pos), dev(v0), s.cell, 0.5, MASS, 2,
+                                 phi0=PHI0, m_rep=MREP, r_cluster=0.0, nu=s.nu, kT=s.kT,
+                                 n_electrons=s.n_electrons)
+    fr = md.velocity_verlet(s.pos, v0, s.cell, md.krylov_forces(s, workers=1, phi0=PHI0), MASS,
+                            0.5, 2)
+    dF = np.abs(np_(F) - fr[-1].F).max()
+    dx = np.abs(_min_image(np_(pos) - fr[-1].pos, s.cell)).max()
+    log(f"[md whole cell] |dF| {dF:.3e}, |dx| {dx:.3e}")
+    assert dF <= F_TOL and dx <= 1e-10
+    assert all(abs(th[k, 0] - f.E_pot) / s.n_atoms <= E_TOL for k, f in enumerate(fr))
+
+
+def test_md_and_pair_errors():
+    torch = torch_cuda()
+    from paper_1210_1531_amd import Context, MagError, model
+    s = gs.make("tiny")
+    ctx = Context()
+    x = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(x)
+    with pytest.raises(MagError):
+        ctx.pair_repulsion(PHI0, MREP)  # no build yet
+    kw = dict(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    for dt, mass, steps in ((0.0, MASS, 1), (0.5, -1.0, 1), (0.5, MASS, -1)):
+        with pytest.raises(MagError):
+            ctx.md_run(model.sk_model(), x, v, s.cell, dt, mass, steps, **kw)
+    with pytest.raises(MagError):
+        ctx.md_run(model.sk_model(), x, v, s.cell, 0.5, MASS, 1, phi0=1.0, m_rep=0.0, **kw)
+    ctx.sk_build(model.sk_model(), x, s.cell)
+    with pytest.raises(MagError):
+        ctx.pair_repulsion(PHI0, -4.0)
+    E, _, _ = ctx.pair_repulsion(0.0, MREP)  # no repulsion: zero energy
+    assert E == 0.0
