@@ -139,6 +139,18 @@ def main(argv=None):
     ctx.sk_build(sk, pos, s.cell)
     rowptr, colind, H, S = ctx.sk_get_csr()
     ctx.set_system(rowptr, colind, H, S, pos=pos, cell=s.cell, r_cluster=s.r_cluster)
+    # set-up (SK build and set_system: pattern, blocks, clusters) timed on its
+    # own, outside the step, after the first (warm-up) build above
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sk_build(sk, pos, s.cell)
+    torch.cuda.synchronize()
+    t_skb = (time.perf_counter() - t0) * 1e3
+    rowptr, colind, H, S = ctx.sk_get_csr()
+    t0 = time.perf_counter()
+    ctx.set_system(rowptr, colind, H, S, pos=pos, cell=s.cell, r_cluster=s.r_cluster)
+    torch.cuda.synchronize()
+    t_sys = (time.perf_counter() - t0) * 1e3
     st0 = ctx.stats()
     opts = dict(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow=args.workflow,
                 schedule=args.schedule)
@@ -285,6 +297,12 @@ def main(argv=None):
             "fp64_frac": fp64_tflops / FP64_PEAK_TFLOPS,
         },
     }
+    _, _, nu_eff = ctx.spectra()
+    nu_eff = nu_eff.cpu().numpy() if hasattr(nu_eff, "cpu") else np.asarray(nu_eff)
+    out["setup_ms"] = {"sk_build": t_skb, "set_system": t_sys}
+    out["nu_eff"] = {"min": int(nu_eff.min()), "mean": float(nu_eff.mean()),
+                     "max": int(nu_eff.max())}
+    out["device_bytes"] = int(ctx.stats()["device_bytes"])
     # ICOHP per block of the pattern (the next row after the hot path): one
     # thread per block, reading rho (128 B), the H block (128 B), the column
     # index and two positions, writing three values
