@@ -176,12 +176,17 @@ def energies(sysm: System, cd, mu):
     return E, E - sysm.kT * S_ent, S_ent, N
 
 
-def forces(sysm: System, rho, pi):
-    """F_I = -sum_p [rho_p dH_p/dR_I - pi_p dS_p/dR_I] over the CSR pattern."""
+def forces(sysm: System, rho, pi, rows=None):
+    """F_I = -sum_p [rho_p dH_p/dR_I - pi_p dS_p/dR_I] over the CSR pattern.
+
+    rows: block rows to contract (all if None).  F_I is complete when the
+    rows of I and of every pattern neighbour of I are among them, and only
+    their entries of rho and pi are read.
+    """
     n = sysm.n_atoms
     dA = np.zeros((n, 3))
     H = sysm.H
-    for J in range(n):
+    for J in (range(n) if rows is None else rows):
         ks = sysm.rows[J]
         nb = ks.size
         for t, K in enumerate(ks):
@@ -236,7 +241,7 @@ def icohp(sysm: System, rho):
     return np.array(B), np.array(Bs), np.array(Bp)
 
 
-def cohp(sysm: System, cd, energies, eta):
+def cohp(sysm: System, cd, energies, eta, atoms=None):
     """Energy-resolved crystal orbital Hamiltonian population, Eq. 4, at
     z = e + i eta (eta > 0 in place of the limit i0).
 
@@ -245,13 +250,14 @@ def cohp(sysm: System, cd, energies, eta):
     with the Galerkin column G_{Kb;j}(z) = sum_k Y_{Kb,k} d_k / (z - eps_k) of
     column j = (J, a) (its pattern rows are cd["ypd"]).  g_s = 2 as in rho, so
     that integrating against f(e - mu) gives the ICOHP of Eq. 5.  Returns an
-    array (blocks in block-CSR order, energies).
+    array (blocks in block-CSR order, energies); with `atoms`, the blocks of
+    those block rows only, in the given order (cd needs their columns only).
     """
     H = sysm.H
     z = np.asarray(energies, dtype=np.float64) + 1j * eta
     where = {int(j): i for i, j in enumerate(cd["cols"])}
     out = []
-    for J in range(sysm.n_atoms):
+    for J in (range(sysm.n_atoms) if atoms is None else atoms):
         for t, _ in enumerate(sysm.rows[J]):
             acc = np.zeros(z.size)
             for a in range(NORB):

@@ -159,6 +159,37 @@ def test_forces_match_oracle_and_sum_to_zero():
     assert np.abs(F.sum(axis=0)).max() < 1e-9
 
 
+def test_forces_and_cohp_sampled_at_full_size_config2():
+    """The benchmark cell in the launch configuration bench.py times: forces of
+    sampled atoms from the oracle's columns of those atoms and their pattern
+    neighbours, contracted at the GPU's mu; COHP(e) of the sampled atoms'
+    blocks from the oracle's columns of those atoms."""
+    import os
+    from oracle import solve
+    from paper_1210_1531_amd import model
+    s, sysm = oracle_system(2)
+    ctx = gpu_context(s)
+    mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, workflow="store")
+    F = np_(ctx.forces(model.sk_model()))
+    e = np.array([-9.0, -3.0, 0.0, 4.0])
+    C = np_(ctx.cohp(e, 0.05))
+    pick = np.sort(np.random.default_rng(11).choice(s.n_atoms, 6, replace=False))
+    need = np.unique(np.concatenate([sysm.rows[I] for I in pick]))
+    cols = (4 * need[:, None] + np.arange(4)[None, :]).ravel()
+    cd = solve.column_data(sysm, cols, workers=min(16, os.cpu_count() or 1))
+    rho_o, pi_o = solve.density_on_pattern(sysm, cd, mu)
+    F_o = solve.forces(sysm, rho_o, pi_o, rows=need)
+    dF = np.abs(F[pick] - F_o[pick]).max()
+    C_o = solve.cohp(sysm, cd, e, 0.05, atoms=pick)
+    bptr = np.concatenate([[0], np.cumsum([len(sysm.rows[J]) for J in range(s.n_atoms)])])
+    blocks = np.concatenate([np.arange(bptr[J], bptr[J + 1]) for J in pick])
+    dC = np.abs(C[blocks] - C_o).max()
+    log(f"[config2 sampled] {pick.size} atoms ({need.size} with neighbours): max |dF| {dF:.3e}, "
+        f"max |dC| {dC:.3e} over {blocks.size} blocks")
+    assert dF <= F_TOL
+    assert dC <= COHP_TOL
+
+
 def test_sampled_columns_at_full_size_config2():
     # the benchmark workload: every column on the GPU, a sample of columns
     # (largest, smallest and random clusters) recomputed one by one by the oracle
