@@ -119,7 +119,7 @@ def cpu_baseline(struct, target_s):
 def main(argv=None):
     args = parse(argv)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (one MI355X); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
     import numpy as np
