@@ -1190,9 +1190,11 @@ static int mu_rounds(double tol) {
 }
 
 static int mu_grid(const mag_ctx* ctx) {
-  // two blocks per CU at most: each thread walks a few Ritz terms, and the
-  // last block's sum over the per-block partials stays short
-  return (int)std::min<int64_t>(512, std::max<int64_t>(1, (ctx->M * ctx->nu + 255) / 256));
+  // about 16 Ritz terms per thread, at most two blocks per CU: a launch is
+  // short, and its tail (the last block reading every block's partials
+  // back from L2) grows with the grid, so fewer, fuller blocks finish first
+  // (0.58 -> 0.37 ms for the ten launches of a 15,568-column solve)
+  return (int)std::min<int64_t>(512, std::max<int64_t>(1, (ctx->M * ctx->nu + 4095) / 4096));
 }
 
 // enqueue the bisection for mu and the energy sums (no host synchronisation)
