@@ -909,9 +909,10 @@ int mag_sk_vjp(mag_ctx* ctx, const double* pos, const double* gH, const double* 
     pgs = dgs.as<double>();
   }
   ALLOC(dgr, sizeof(double) * 3 * n);
-  HIPCHK(launch_sk_vjp(ctx->sk_model, ctx->sk_pos.as<double>(), n, ctx->sk_cell,
+  ALLOC(ctx->f_part, sizeof(double) * 3 * std::max<int64_t>(ctx->sk_nblk, 1));
+  HIPCHK(launch_sk_vjp(ctx->sk_model, ctx->sk_pos.as<double>(), n, ctx->sk_nblk, ctx->sk_cell,
                        ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), bt.as<int32_t>(),
-                       pgh, pgs, 1.0, dgr.as<double>(), ctx->stream));
+                       pgh, pgs, 1.0, ctx->f_part.as<double>(), dgr.as<double>(), ctx->stream));
   TRY(take_errors(ctx, "mag_sk_vjp"));
   TRY(copy_out(ctx, grad, dgr.p, sizeof(double) * 3 * n, mem_kind));
   return sync(ctx);
@@ -1686,12 +1687,14 @@ int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind)
   if (!ctx->has_pos) return fail(ctx, MAG_EINVAL, "forces need mag_system.pos");
   TRY(ensure_density(ctx));
   Timer tm(ctx->stream);
-  DevBuf grad, out;
-  ALLOC(grad, sizeof(double) * 3 * ctx->N);
-  HIPCHK(launch_sk_vjp(to_dev(*model), ctx->pos.as<double>(), ctx->N, ctx->cell,
+  DevBuf out;
+  ALLOC(ctx->f_grad, sizeof(double) * 3 * ctx->N);
+  ALLOC(ctx->f_part, sizeof(double) * 3 * std::max<int64_t>(ctx->nblk, 1));
+  DevBuf& grad = ctx->f_grad;
+  HIPCHK(launch_sk_vjp(to_dev(*model), ctx->pos.as<double>(), ctx->N, ctx->nblk, ctx->cell,
                        ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(),
                        ctx->btrans.as<int32_t>(), ctx->rho.as<double>(), ctx->pi.as<double>(),
-                       -1.0, grad.as<double>(), ctx->stream));
+                       -1.0, ctx->f_part.as<double>(), grad.as<double>(), ctx->stream));
   double* dst = F;
   if (mem_kind == MAG_HOST) {
     ALLOC(out, sizeof(double) * 3 * ctx->N);
@@ -1923,7 +1926,7 @@ int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
                           &ctx->tmp_out, &ctx->k_trid, &ctx->k_evu, &ctx->k_rot,
                           &ctx->k_sweep, &ctx->k_qlst, &ctx->k_fbl, &ctx->k_fbc,
                           &ctx->md_x, &ctx->md_v, &ctx->md_F, &ctx->md_Frep, &ctx->md_e,
-                          &ctx->md_sum};
+                          &ctx->md_sum, &ctx->f_part, &ctx->f_grad};
   for (const DevBuf* b : bufs) bytes += (int64_t)b->bytes;
   ctx->stats.device_bytes = bytes;
   *out = ctx->stats;

@@ -263,10 +263,10 @@ hipError_t launch_md_drift(double* x, const double* v, int64_t n, double dt, con
 hipError_t launch_axpy(double* y, const double* x, int64_t n, double a, hipStream_t s);
 hipError_t launch_sum(const double* a, int64_t n, int squares, double* out, hipStream_t s);
 extern const double AMU_A2_FS2_EV;
-hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
-                         const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
-                         const double* gH, const double* gS, double sign_gS, double* grad,
-                         hipStream_t s);
+hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, int64_t nblk,
+                         const double cell[3], const int32_t* bptr, const int32_t* bcol,
+                         const int32_t* btrans, const double* gH, const double* gS, double sign_gS,
+                         double* part, double* grad, hipStream_t s);
 
 // system conversion
 hipError_t launch_check_layout(const int64_t* rowptr, const int32_t* colind, int64_t n,
@@ -308,6 +308,7 @@ struct mag_ctx {
   mag::SKModelDev sk_model{};
   mag::DevBuf sk_pos, sk_bptr, sk_bcol, sk_rowptr, sk_colind, sk_H, sk_S;
   mag::DevBuf md_x, md_v, md_F, md_Frep, md_e, md_sum;  // MD step state
+  mag::DevBuf f_part, f_grad;  // force contraction: per-block parts, per-atom sums
 
   // system
   bool has_system = false;

@@ -377,18 +377,31 @@ __global__ void sk_values_kernel(SKModelDev m, const double* pos, int64_t n, Box
   }
 }
 
-// grad[I] = sum over blocks (I,K) and (K,I) of g . d(block)/dR_I
-__global__ void sk_vjp_kernel(SKModelDev m, const double* pos, int64_t n, Box box,
-                              const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
-                              const double* gH, const double* gS, double sgn, double* grad) {
-  const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (I >= n) return;
+// grad[I] = sum over blocks (I,K) and (K,I) of g . d(block)/dR_I, in two
+// passes: one thread per block b = (I, t) of the pattern writes the pair's
+// two terms (block (I,K) and its transpose (K,I) in row K) to part[b], then
+// one thread per atom adds its row's parts in block order (deterministic).
+// One thread per atom alone would leave most of the device idle: its ~17
+// blocks x 4 contractions run as one serial chain per thread.
+__global__ void sk_vjp_pair_kernel(SKModelDev m, const double* pos, int64_t n, int64_t nblk,
+                                   Box box, const int32_t* bptr, const int32_t* bcol,
+                                   const int32_t* btrans, const double* gH, const double* gS,
+                                   double sgn, double* part) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  int64_t lo = 0, hi = n - 1;  // last row I with bptr[I] <= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (bptr[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t I = lo;
   const int64_t b0 = bptr[I];
   const int nb = bptr[I + 1] - bptr[I];
+  const int t = (int)(b - b0);
+  const int K = bcol[b];
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int t = 0; t < nb; ++t) {
-    const int K = bcol[b0 + t];
-    if (K == I) continue;
+  if (K != I) {
     double dx = pos[3 * K] - pos[3 * I], dy = pos[3 * K + 1] - pos[3 * I + 1],
            dz = pos[3 * K + 2] - pos[3 * I + 2];
     min_image(box, dx, dy, dz);
@@ -397,9 +410,9 @@ __global__ void sk_vjp_kernel(SKModelDev m, const double* pos, int64_t n, Box bo
       double Gh[4][4], Gs[4][4];
       for (int a = 0; a < 4; ++a) {
         const int64_t r0 = 16 * b0 + 4 * (int64_t)a * nb + 4 * t;
-        for (int b = 0; b < 4; ++b) {
-          Gh[a][b] = gH[r0 + b];
-          Gs[a][b] = sgn * gS[r0 + b];
+        for (int c = 0; c < 4; ++c) {
+          Gh[a][c] = gH[r0 + c];
+          Gs[a][c] = sgn * gS[r0 + c];
         }
       }
       double oh[3], os[3];
@@ -409,16 +422,16 @@ __global__ void sk_vjp_kernel(SKModelDev m, const double* pos, int64_t n, Box bo
     }
     // block (K, I) in row K: depends on R_I through d' = R_I - R_K = -d -> plus sign
     {
-      const int bt = btrans[b0 + t];
+      const int bt = btrans[b];
       const int64_t k0 = bptr[K];
       const int nbk = bptr[K + 1] - bptr[K];
       const int tt = (int)(bt - k0);
       double Gh[4][4], Gs[4][4];
       for (int a = 0; a < 4; ++a) {
         const int64_t r0 = 16 * k0 + 4 * (int64_t)a * nbk + 4 * tt;
-        for (int b = 0; b < 4; ++b) {
-          Gh[a][b] = gH[r0 + b];
-          Gs[a][b] = sgn * gS[r0 + b];
+        for (int c = 0; c < 4; ++c) {
+          Gh[a][c] = gH[r0 + c];
+          Gs[a][c] = sgn * gS[r0 + c];
         }
       }
       double oh[3], os[3];
@@ -427,6 +440,16 @@ __global__ void sk_vjp_kernel(SKModelDev m, const double* pos, int64_t n, Box bo
       for (int c = 0; c < 3; ++c) acc[c] += oh[c] + os[c];
     }
   }
+  for (int c = 0; c < 3; ++c) part[3 * b + c] = acc[c];
+}
+
+__global__ void sk_vjp_sum_kernel(const int32_t* bptr, int64_t n, const double* part,
+                                  double* grad) {
+  const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t b = bptr[I]; b < bptr[I + 1]; ++b)
+    for (int c = 0; c < 3; ++c) acc[c] += part[3 * b + c];
   for (int c = 0; c < 3; ++c) grad[3 * I + c] = acc[c];
 }
 
@@ -502,13 +525,17 @@ hipError_t launch_sk_values(const SKModelDev& m, const double* pos, int64_t n,
                      box, bptr, bcol, H, S);
   return hipGetLastError();
 }
-hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, const double cell[3],
-                         const int32_t* bptr, const int32_t* bcol, const int32_t* btrans,
-                         const double* gH, const double* gS, double sign_gS, double* grad,
-                         hipStream_t s) {
+hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, int64_t nblk,
+                         const double cell[3], const int32_t* bptr, const int32_t* bcol,
+                         const int32_t* btrans, const double* gH, const double* gS, double sign_gS,
+                         double* part, double* grad, hipStream_t s) {
   Box box{{cell[0], cell[1], cell[2]}};
-  hipLaunchKernelGGL(sk_vjp_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, m, pos, n, box,
-                     bptr, bcol, btrans, gH, gS, sign_gS, grad);
+  if (n <= 0) return hipSuccess;
+  if (nblk > 0)
+    hipLaunchKernelGGL(sk_vjp_pair_kernel, dim3(blocks_for(nblk, STPB)), dim3(STPB), 0, s, m, pos,
+                       n, nblk, box, bptr, bcol, btrans, gH, gS, sign_gS, part);
+  hipLaunchKernelGGL(sk_vjp_sum_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, bptr, n, part,
+                     grad);
   return hipGetLastError();
 }
 
