@@ -139,8 +139,9 @@ typedef struct {
 /* Build pattern and values of H and S from positions on the device.
  * pos: n_atoms x 3 doubles (mem_kind); cell: 3 box lengths (host).
  * On success *nnz_out = number of CSR nonzeros; fetch the CSR with
- * mag_sk_get_csr.  Errors: MAG_EINVAL (sizes, 2 r_cut >= box, more than
- * MAG_BLOCKS_MAX atoms in a block row), MAG_ENONFINITE, MAG_ENOMEM. */
+ * mag_sk_get_csr.  Errors: MAG_EINVAL (sizes, 2 r_cut >= box),
+ * MAG_EUNSUPPORTED (more than MAG_BLOCKS_MAX atoms in a block row),
+ * MAG_ENONFINITE, MAG_ENOMEM. */
 int mag_sk_build(mag_ctx* ctx, const mag_sk_model* model, int64_t n_atoms,
                  const double* pos, const double cell[3], int mem_kind,
                  int64_t* nnz_out);

@@ -822,6 +822,9 @@ int mag_sk_build(mag_ctx* ctx, const mag_sk_model* model, int64_t n_atoms, const
   TRY(take_errors(ctx, "mag_sk_build"));
   hb[0] = 0;
   for (int64_t i = 0; i < n; ++i) {
+    if (hc[i] > BLOCKS_MAX)
+      return fail(ctx, MAG_EUNSUPPORTED, "atom " + std::to_string(i) +
+                                             " has more than MAG_BLOCKS_MAX pattern blocks");
     if ((int64_t)hb[i] + hc[i] > INT32_MAX / 32)
       return fail(ctx, MAG_EUNSUPPORTED, "too many blocks");
     hb[i + 1] = hb[i] + hc[i];

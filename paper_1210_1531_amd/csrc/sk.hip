@@ -345,34 +345,36 @@ __global__ void icohp_kernel(SKModelDev m, const double* pos, int64_t n, int64_t
   if (Bpi) Bpi[b] = pi;
 }
 
+// one thread per block (atom J, block t < 32 of its row)
 __global__ void sk_values_kernel(SKModelDev m, const double* pos, int64_t n, Box box,
                                  const int32_t* bptr, const int32_t* bcol, double* H, double* S) {
-  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t J = idx >> 5;
   if (J >= n) return;
+  const int t = (int)(idx & 31);
   const int64_t b0 = bptr[J];
   const int nb = bptr[J + 1] - bptr[J];
-  for (int t = 0; t < nb; ++t) {
-    const int K = bcol[b0 + t];
-    double Bh[4][4], Bs[4][4];
-    if (K == J) {
-      for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) {
-          Bh[a][b] = (a == b) ? (a == 0 ? m.es : m.ep) : 0.0;
-          Bs[a][b] = (a == b) ? 1.0 : 0.0;
-        }
-    } else {
-      double dx = pos[3 * K] - pos[3 * J], dy = pos[3 * K + 1] - pos[3 * J + 1],
-             dz = pos[3 * K + 2] - pos[3 * J + 2];
-      min_image(box, dx, dy, dz);
-      two_center(m, m.vh, dx, dy, dz, Bh);
-      two_center(m, m.vs, dx, dy, dz, Bs);
-    }
-    for (int a = 0; a < 4; ++a) {
-      const int64_t r0 = 16 * b0 + 4 * (int64_t)a * nb + 4 * t;
-      for (int b = 0; b < 4; ++b) {
-        H[r0 + b] = Bh[a][b];
-        S[r0 + b] = Bs[a][b];
+  if (t >= nb) return;
+  const int K = bcol[b0 + t];
+  double Bh[4][4], Bs[4][4];
+  if (K == J) {
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        Bh[a][c] = (a == c) ? (a == 0 ? m.es : m.ep) : 0.0;
+        Bs[a][c] = (a == c) ? 1.0 : 0.0;
       }
+  } else {
+    double dx = pos[3 * K] - pos[3 * J], dy = pos[3 * K + 1] - pos[3 * J + 1],
+           dz = pos[3 * K + 2] - pos[3 * J + 2];
+    min_image(box, dx, dy, dz);
+    two_center(m, m.vh, dx, dy, dz, Bh);
+    two_center(m, m.vs, dx, dy, dz, Bs);
+  }
+  for (int a = 0; a < 4; ++a) {
+    const int64_t r0 = 16 * b0 + 4 * (int64_t)a * nb + 4 * t;
+    for (int c = 0; c < 4; ++c) {
+      H[r0 + c] = Bh[a][c];
+      S[r0 + c] = Bs[a][c];
     }
   }
 }
@@ -521,7 +523,8 @@ hipError_t launch_sk_values(const SKModelDev& m, const double* pos, int64_t n,
                             const double cell[3], const int32_t* bptr, const int32_t* bcol,
                             double* H, double* S, hipStream_t s) {
   Box box{{cell[0], cell[1], cell[2]}};
-  hipLaunchKernelGGL(sk_values_kernel, dim3(blocks_for(n, STPB)), dim3(STPB), 0, s, m, pos, n,
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sk_values_kernel, dim3(blocks_for(n * 32, STPB)), dim3(STPB), 0, s, m, pos, n,
                      box, bptr, bcol, H, S);
   return hipGetLastError();
 }

@@ -36,47 +36,49 @@ __global__ void check_layout_kernel(const int64_t* rowptr, const int32_t* colind
   if (!ok || !self) atomicOr(err, (int)KERR_LAYOUT);
 }
 
+// one thread per value of the block layout: atom J, its block t (< 32) and
+// the value o of the block's 32 (quarters of 8 doubles: H columns 0-1, H
+// columns 2-3, S columns 0-1, S columns 2-3, each holding rows 0..3 as
+// pairs, so that the four threads of an atom row in the Krylov SpMV read one
+// contiguous 64-byte run per 16-byte load); a block's 32 stores are
+// consecutive
 __global__ void to_blocks_kernel(const int64_t* rowptr, const double* H, const double* S,
                                  int64_t n, const int32_t* bptr, double* bval) {
-  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t J = idx >> 10;
   if (J >= n) return;
-  const int nb = bptr[J + 1] - bptr[J];
-  for (int t = 0; t < nb; ++t) {
-    double* dst = bval + (int64_t)(bptr[J] + t) * 32;
-    // quarters of 8 doubles: H columns 0-1, H columns 2-3, S columns 0-1,
-    // S columns 2-3, each holding rows 0..3 as pairs; the four threads of an
-    // atom row read one contiguous 64-byte run per 16-byte load
-    for (int a = 0; a < NORB; ++a) {
-      const int64_t ra = rowptr[NORB * J + a] + 4 * t;
-      for (int be = 0; be < NORB; ++be) {
-        const int o = (be >> 1) * 8 + 2 * a + (be & 1);
-        dst[o] = H[ra + be];
-        dst[16 + o] = S[ra + be];
-      }
-    }
-  }
+  const int t = (int)((idx >> 5) & 31), o = (int)(idx & 31);
+  if (t >= bptr[J + 1] - bptr[J]) return;
+  const int q = o & 15, r = q & 7;
+  const int a = r >> 1, be = (q >> 3) * 2 + (r & 1);
+  const double* src = (o < 16) ? H : S;
+  bval[(int64_t)(bptr[J] + t) * 32 + o] = src[rowptr[NORB * J + a] + 4 * t + be];
 }
 
+// one thread per block (atom J, block t < 32): the position of block (K, J)
+// in row K, by binary search
 __global__ void block_transpose_kernel(const int32_t* bptr, const int32_t* bcol, int64_t n,
                                        int32_t* btrans, int32_t* err) {
-  const int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t J = idx >> 5;
   if (J >= n) return;
-  for (int b = bptr[J]; b < bptr[J + 1]; ++b) {
-    const int K = bcol[b];
-    int lo = bptr[K], hi = bptr[K + 1] - 1, found = -1;
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int v = bcol[mid];
-      if (v == (int)J) {
-        found = mid;
-        break;
-      }
-      if (v < (int)J) lo = mid + 1;
-      else hi = mid - 1;
+  const int t = (int)(idx & 31);
+  if (t >= bptr[J + 1] - bptr[J]) return;
+  const int b = bptr[J] + t;
+  const int K = bcol[b];
+  int lo = bptr[K], hi = bptr[K + 1] - 1, found = -1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = bcol[mid];
+    if (v == (int)J) {
+      found = mid;
+      break;
     }
-    btrans[b] = found;
-    if (found < 0) atomicOr(err, (int)KERR_LAYOUT);
+    if (v < (int)J) lo = mid + 1;
+    else hi = mid - 1;
   }
+  btrans[b] = found;
+  if (found < 0) atomicOr(err, (int)KERR_LAYOUT);
 }
 
 __global__ void check_finite_kernel(const double* x, int64_t n, int32_t* err) {
@@ -118,13 +120,15 @@ hipError_t launch_check_layout(const int64_t* rowptr, const int32_t* colind, int
 }
 hipError_t launch_to_blocks(const int64_t* rowptr, const double* H, const double* S, int64_t n,
                             const int32_t* bptr, double* bval, hipStream_t s) {
-  hipLaunchKernelGGL(to_blocks_kernel, dim3(nblocks(n, 128)), dim3(128), 0, s, rowptr, H, S, n,
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(to_blocks_kernel, dim3(nblocks(n * 1024, 256)), dim3(256), 0, s, rowptr, H, S, n,
                      bptr, bval);
   return hipGetLastError();
 }
 hipError_t launch_block_transpose(const int32_t* bptr, const int32_t* bcol, int64_t n,
                                   int32_t* btrans, int32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(block_transpose_kernel, dim3(nblocks(n, 128)), dim3(128), 0, s, bptr, bcol,
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_transpose_kernel, dim3(nblocks(n * 32, 256)), dim3(256), 0, s, bptr, bcol,
                      n, btrans, err);
   return hipGetLastError();
 }
