@@ -316,7 +316,7 @@ int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigm
  * mag_icohp (nnz / 16 blocks).  Integrated against f(e - mu) it tends to the
  * ICOHP B as eta -> 0 (Eq. 5).  Needs the pattern rows kept by the store
  * workflow: MAG_ESTATE after a solve with MAG_WORKFLOW_RECOMPUTE (or before
- * any solve); MAG_EINVAL for ne <= 0, eta <= 0 or non-finite energies. */
+ * any solve); MAG_EINVAL for ne <= 0, eta < 1e-100 or non-finite energies. */
 int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C, int mem_kind);
 
 /* Green's-function columns by a second solver of Eq. 1: the conjugate

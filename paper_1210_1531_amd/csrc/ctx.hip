@@ -1744,7 +1744,8 @@ int mag_cohp(mag_ctx* ctx, const double* energies, int ne, double eta, double* C
   TRY(ensure_system(ctx));
   TRY(check_mem_kind(ctx, mem_kind));
   if (!energies || !C || ne <= 0) return fail(ctx, MAG_EINVAL, "energies, ne > 0 and C required");
-  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(ctx, MAG_EINVAL, "eta must be > 0");
+  if (!(eta >= 1e-100) || !std::isfinite(eta))
+    return fail(ctx, MAG_EINVAL, "eta must be finite and >= 1e-100");
   for (int q = 0; q < ne; ++q)
     if (!std::isfinite(energies[q])) return fail(ctx, MAG_EINVAL, "energies must be finite");
   if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve: call mag_solve_columns first");

@@ -795,7 +795,14 @@ __global__ __launch_bounds__(ETPB) void cohp_kernel(const double* bval, const in
     double acc = 0.0;
     for (int idx = 0; idx < 4 * nu; ++idx) {
       const double d = x - e_s[idx];
-      acc = fma(c_s[idx], 1.0 / fma(d, d, eta2), acc);
+      // d^2 + eta^2 is a normal positive number (eta >= 1e-100 is checked
+      // on entry): the hardware reciprocal and two Newton steps give it to
+      // full precision with nothing to special-case
+      const double den = fma(d, d, eta2);
+      double r = __builtin_amdgcn_rcp(den);
+      r = fma(r, fma(-den, r, 1.0), r);
+      r = fma(r, fma(-den, r, 1.0), r);
+      acc = fma(c_s[idx], r, acc);
     }
     out[b * ne + q] = scale * acc;
   }
