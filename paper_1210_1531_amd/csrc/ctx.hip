@@ -24,14 +24,19 @@ int fail(mag_ctx* ctx, int code, const std::string& msg) {
       return fail(ctx, MAG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
   } while (0)
 
-// grow-only device allocation; a buffer that moves invalidates captured graphs
-#define ALLOC(buf, bytes)                                                                  \
+// grow-only device allocation; a buffer that moves invalidates captured graphs.
+// A buffer outgrown by a new system (the pattern of an MD frame gaining a
+// few blocks) is replaced with 1/16 headroom, so that the next small growth
+// does not free and allocate it again.
+#define ALLOC(buf, nbytes)                                                                  \
   do {                                                                                     \
     void* old_p_ = (buf).p;                                                                \
-    if ((buf).reserve(bytes) != hipSuccess) {                                              \
+    const size_t want_ = (size_t)(nbytes);                                                  \
+    const size_t ask_ = ((buf).p && want_ > (buf).bytes) ? want_ + want_ / 16 : want_;     \
+    if ((buf).reserve(ask_) != hipSuccess) {                                               \
       (void)hipGetLastError();                                                             \
       return fail(ctx, MAG_ENOMEM, std::string("device allocation of ") +                 \
-                                       std::to_string((size_t)(bytes)) + " bytes failed"); \
+                                       std::to_string(ask_) + " bytes failed");            \
     }                                                                                      \
     if ((buf).p != old_p_) ++ctx->alloc_gen;                                               \
   } while (0)
