@@ -167,3 +167,21 @@ def test_md_and_pair_errors():
         ctx.pair_repulsion(PHI0, -4.0)
     E, _, _ = ctx.pair_repulsion(0.0, MREP)  # no repulsion: zero energy
     assert E == 0.0
+
+
+def test_md_host_arrays_equal_device_arrays():
+    """The same run with host (NumPy) and device (torch) arrays: bitwise equal."""
+    torch = torch_cuda()
+    from paper_1210_1531_amd import Context, model
+    s = gs.make("tiny")
+    v0 = gs.random_velocities(s.n_atoms, _sigma(300.0), 24)
+    kw = dict(phi0=PHI0, m_rep=MREP, r_cluster=s.r_cluster, nu=s.nu, kT=s.kT,
+              n_electrons=s.n_electrons)
+    host = Context(device_outputs=False)
+    xh, vh, Fh, th_h = host.md_run(model.sk_model(), s.pos, v0, s.cell, 0.5, MASS, 2, **kw)
+    dev = Context()
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    xd, vd, Fd, th_d = dev.md_run(model.sk_model(), t(s.pos), t(v0), s.cell, 0.5, MASS, 2, **kw)
+    assert isinstance(xh, np.ndarray)
+    assert np.array_equal(xh, np_(xd)) and np.array_equal(vh, np_(vd))
+    assert np.array_equal(Fh, np_(Fd)) and np.array_equal(th_h, th_d)
