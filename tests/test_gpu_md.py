@@ -185,3 +185,16 @@ def test_md_host_arrays_equal_device_arrays():
     assert isinstance(xh, np.ndarray)
     assert np.array_equal(xh, np_(xd)) and np.array_equal(vh, np_(vd))
     assert np.array_equal(Fh, np_(Fd)) and np.array_equal(th_h, th_d)
+
+
+def test_sk_build_rejects_overfull_block_rows():
+    """40 atoms within 1.2 A of a point: every block row would exceed the
+    32-block limit; the build reports it instead of truncating the rows."""
+    torch_cuda()
+    from paper_1210_1531_amd import Context, MagError, model
+    rng = np.random.default_rng(2)
+    pos = 5.0 + rng.uniform(-0.7, 0.7, size=(40, 3))
+    ctx = Context(device_outputs=False)
+    with pytest.raises(MagError) as e:
+        ctx.sk_build(model.sk_model(), pos, (10.0, 10.0, 10.0))
+    assert "MAG_EUNSUPPORTED" in str(e.value)
