@@ -89,9 +89,10 @@ def cpu_baseline(struct, target_s):
     """Oracle (plain NumPy/SciPy, mode K) on a bounded sample of the workload's columns."""
     import numpy as np
 
-    from oracle import solve
+    from oracle import pool, solve
+    pool.start()  # before this process touches the GPU: the workers fork from a clean server
     cores = min(16, len(os.sched_getaffinity(0)))
-    sysm = solve.build_system(struct)
+    sysm = solve.geometry(struct)
     M = sysm.M
     probe = np.arange(0, M, max(1, M // 16))[:16]
     t0 = time.perf_counter()
@@ -123,15 +124,18 @@ def main(argv=None):
                           "n_gpus": args.gpus}), flush=True)
         return 2
     import numpy as np
-    import torch
 
     import gen
-    from paper_1210_1531_amd import Context, model
 
     key = int(args.config) if args.config.isdigit() else args.config
     s = gen.make(key, nu=args.nu)
     print(f"# workload {s.name}: {s.n_atoms} atoms, {4 * s.n_atoms} columns, nu {s.nu}",
           file=sys.stderr, flush=True)
+    # the oracle's CPU leg runs first, before anything here initialises the GPU
+    cpu = None if args.no_cpu else cpu_baseline(s, args.cpu_seconds)
+    import torch
+
+    from paper_1210_1531_amd import Context, model
     torch.cuda.init()
     ctx = Context(device=0)
     pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
@@ -361,8 +365,8 @@ def main(argv=None):
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 

@@ -15,8 +15,6 @@ and forces follow from the Slater-Koster derivatives:
 """
 from __future__ import annotations
 
-import multiprocessing as mp
-import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -25,6 +23,7 @@ import scipy.linalg as sla
 from . import fermi as _fermi
 from . import krylov as _kry
 from . import neighbors as _nb
+from . import pool as _pool
 from . import sk as _sk
 
 NORB = _nb.NORB
@@ -67,23 +66,58 @@ def build_system(struct, params: _sk.SKParams = _sk.CARBON, nu=None, r_cluster=N
 # --------------------------------------------------------------------------
 # per-atom work (the four columns of an atom share its cluster)
 # --------------------------------------------------------------------------
+@dataclass
+class Geometry:
+    """What one column needs: positions, box, cluster radius, Krylov
+    dimension and the model (no global matrices), so that sampled columns of
+    cells far too large for the dense pattern build can be computed."""
+    pos: np.ndarray
+    cell: np.ndarray
+    r_cluster: float
+    nu: int
+    params: _sk.SKParams
+    kT: float = 0.1
+    n_electrons: float = 0.0
+    rows: list = None  # block rows of every atom, or None (found per column)
+
+    @property
+    def n_atoms(self):
+        return self.pos.shape[0]
+
+    @property
+    def M(self):
+        return NORB * self.pos.shape[0]
+
+
+def geometry(struct, params: _sk.SKParams = _sk.CARBON, nu=None) -> Geometry:
+    return Geometry(pos=np.asarray(struct.pos, np.float64), cell=np.asarray(struct.cell, np.float64),
+                    r_cluster=struct.r_cluster, nu=struct.nu if nu is None else int(nu),
+                    params=params, kT=struct.kT, n_electrons=struct.n_electrons)
+
+
 _WORK = {}
 
 
+def _block_row(geo, J):
+    nb = _nb.neighbors_of(geo.pos, geo.cell, J, geo.params.r_cut)
+    return np.sort(np.concatenate([nb, [J]])).astype(np.int64)
+
+
 def _atom_columns(args):
-    J, alphas, mode, full = args
-    sysm = _WORK["sys"]
-    atoms = _nb.cluster_of(sysm.pos, sysm.cell, J, sysm.r_cluster)
-    Hc, Sc = _nb.cluster_matrices(sysm.pos, sysm.cell, atoms, sysm.params)
+    J, alphas, pat_atoms, mode, full = args
+    geo = _WORK["geo"]
+    atoms = _nb.cluster_of(geo.pos, geo.cell, J, geo.r_cluster)
+    Hc, Sc = _nb.cluster_matrices(geo.pos, geo.cell, atoms, geo.params)
     jl = int(np.searchsorted(atoms, J))
-    pat_atoms = sysm.rows[J]
+    if pat_atoms is None:
+        pat_atoms = _block_row(geo, J)
     pat_local = np.searchsorted(atoms, pat_atoms)
     pat_rows = (NORB * pat_local[:, None] + np.arange(NORB)[None, :]).ravel()
     out = []
     for a in alphas:
         l = NORB * jl + a
         if mode == "K":
-            res = _kry.column_mode_k(Hc, Sc, l, sysm.nu)
+            res = _kry.column_mode_k(Hc, Sc, l, geo.nu)
         else:
             res = _kry.column_mode_d(Hc, Sc, l)
         ypd = res.Y[pat_rows, :] * res.d[None, :]
@@ -96,35 +130,46 @@ def _atom_columns(args):
     return out
 
 
-def _init_worker():
+def _init_worker(geo):
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:  # pragma: no cover - threadpoolctl is optional
         pass
+    _WORK["geo"] = geo
 
 
-def column_data(sysm: System, cols=None, mode="K", workers=None, full=False):
+def column_data(sysm, cols=None, mode="K", workers=None, full=False):
     """Ritz data for the given global columns (all if None).
 
-    Returns a dict with arrays eps, w (ncols x width, zero-padded), nu_eff,
-    the column ids, and per-column lists ypd (pattern rows x nu_eff) and, if
-    ``full``, the full Ritz vectors and cluster atoms.
+    sysm: a System or a Geometry.  Returns a dict with arrays eps, w (ncols x
+    width, zero-padded), nu_eff, the column ids, and per-column lists ypd
+    (pattern rows x nu_eff) and, if ``full``, the full Ritz vectors and
+    cluster atoms.  With workers > 1 the atoms are spread over fork-server
+    processes (oracle.pool); a worker that dies raises.
     """
     M = sysm.M
     cols = np.arange(M) if cols is None else np.asarray(cols, dtype=np.int64)
     by_atom = {}
     for j in cols:
         by_atom.setdefault(int(j) // NORB, []).append(int(j) % NORB)
-    tasks = [(J, sorted(a), mode, full) for J, a in sorted(by_atom.items())]
-    _WORK["sys"] = sysm
-    workers = workers or int(os.environ.get("ORACLE_WORKERS", os.cpu_count() or 1))
+    rows = getattr(sysm, "rows", None)
+    tasks = [(J, sorted(a), None if rows is None else rows[J], mode, full)
+             for J, a in sorted(by_atom.items())]
+    geo = Geometry(pos=sysm.pos, cell=sysm.cell, r_cluster=sysm.r_cluster, nu=sysm.nu,
+                   params=sysm.params)
+    workers = workers or _pool.default_workers()
     if workers > 1 and len(tasks) > 8:
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers, initializer=_init_worker) as pool:
-            chunks = pool.map(_atom_columns, tasks, chunksize=max(1, len(tasks) // (8 * workers)))
+        with _pool.executor(workers, initializer=_init_worker, initargs=(geo,)) as ex:
+            chunks = list(ex.map(_atom_columns, tasks,
+                                 chunksize=max(1, len(tasks) // (8 * workers))))
     else:
-        chunks = [_atom_columns(t) for t in tasks]
+        saved = _WORK.get("geo")
+        _WORK["geo"] = geo
+        try:
+            chunks = [_atom_columns(t) for t in tasks]
+        finally:
+            _WORK["geo"] = saved
     items = {it["j"]: it for ch in chunks for it in ch}
     width = max([it["eps"].size for it in items.values()] + [1])
     n = cols.size

@@ -11,3 +11,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU-only test")
+
+
+def pytest_sessionstart(session):
+    # the oracle's worker processes fork from a clean server process started
+    # here, before any test touches the GPU
+    from oracle import pool
+    pool.start()
