@@ -233,8 +233,12 @@ __global__ __launch_bounds__(MTPB) void mu_round_kernel(const double* eps, const
 #pragma unroll
       for (int p = 0; p < MPTS; ++p) {
         const double d = fma(E, cp[p], 1.0);
+        // hardware reciprocal and two Newton steps: one step leaves an
+        // error of one sign (r <= 1/d) of order 2^-46, which would bias N(mu)
+        // low by up to N_e 2^-46; after the second the error is rounding
         double r = __builtin_amdgcn_rcp(d);
-        r = fma(r, fma(-d, r, 1.0), r);  // one Newton step
+        r = fma(r, fma(-d, r, 1.0), r);
+        r = fma(r, fma(-d, r, 1.0), r);
         acc[p] = fma(ww, r, acc[p]);
       }
     });

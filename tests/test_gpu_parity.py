@@ -176,7 +176,7 @@ def test_forces_and_cohp_sampled_at_full_size_config2():
     pick = np.sort(np.random.default_rng(11).choice(s.n_atoms, 6, replace=False))
     need = np.unique(np.concatenate([sysm.rows[I] for I in pick]))
     cols = (4 * need[:, None] + np.arange(4)[None, :]).ravel()
-    cd = solve.column_data(sysm, cols, workers=min(16, os.cpu_count() or 1))
+    cd = solve.column_data(sysm, cols)
     rho_o, pi_o = solve.density_on_pattern(sysm, cd, mu)
     F_o = solve.forces(sysm, rho_o, pi_o, rows=need)
     dF = np.abs(F[pick] - F_o[pick]).max()
@@ -190,106 +190,87 @@ def test_forces_and_cohp_sampled_at_full_size_config2():
     assert dC <= COHP_TOL
 
 
-def test_sampled_columns_at_full_size_config2():
-    # the benchmark workload: every column on the GPU, a sample of columns
-    # (largest, smallest and random clusters) recomputed one by one by the oracle
-    from oracle import krylov, neighbors
-    import gen
-    s = gen.make(2)
-    log(f"[config2] {s.n_atoms} atoms")
+def test_config2_every_column_in_the_bench_launch():
+    """The benchmark cell in the launch configuration bench.py times (library
+    schedule and workflow): every pattern entry of rho and pi of all 15,568
+    columns, the spectra, the energies and the electron count against the
+    oracle's columns at the GPU's mu."""
+    from oracle import fermi, solve
+    s, sysm = oracle_system(2)
+    ref = oracle_solution(2)
     ctx = gpu_context(s)
     mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
     eps, w, nu_eff = (np_(x) for x in ctx.spectra())
-    rho, _ = (np_(x) for x in ctx.density_matrix())
-    rowptr = np_(ctx._csr[0])
-    colind = np_(ctx._csr[1])
-    ptr, atoms = (np_(x) for x in ctx.get_clusters())
-    sizes = np.diff(ptr)
-    rng = np.random.default_rng(7)
-    atoms_pick = np.unique(np.concatenate([np.argsort(sizes)[:3], np.argsort(sizes)[-3:],
-                                           rng.choice(s.n_atoms, 10, replace=False)]))
-    worst = 0.0
-    for J in atoms_pick:
-        clus = neighbors.cluster_of(s.pos, s.cell, int(J), s.r_cluster)
-        np.testing.assert_array_equal(clus, atoms[ptr[J]:ptr[J + 1]])
-        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
-        jl = int(np.searchsorted(clus, J))
-        for a in range(4):
-            j = 4 * int(J) + a
-            res = krylov.column_mode_k(Hc, Sc, 4 * jl + a, s.nu)
-            assert res.nu_eff == nu_eff[j]
-            np.testing.assert_allclose(eps[j, :res.nu_eff], res.eps, rtol=0, atol=1e-9)
-            np.testing.assert_allclose(w[j, :res.nu_eff], res.w, rtol=0, atol=1e-10)
-            col, _ = krylov.density_column(res, mu, s.kT)
-            lo, hi = rowptr[j], rowptr[j + 1]
-            rows = np.searchsorted(clus, colind[lo:hi] // 4) * 4 + colind[lo:hi] % 4
-            d = np.abs(rho[lo:hi] - col[rows]).max()
-            worst = max(worst, d)
-    log(f"[config2] sampled {len(atoms_pick)} atoms, max |d rho| {worst:.3e}")
-    assert worst <= RHO_TOL
-    # invariants at full size: closure of every column's weights, electron count
-    sums = np.where(np.arange(w.shape[1])[None, :] < nu_eff[:, None], w, 0.0).sum(axis=1)
-    np.testing.assert_allclose(sums, 2.0, atol=1e-11)
-    assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
+    np.testing.assert_array_equal(nu_eff, ref.cd["nu_eff"])
+    deps = np.abs(eps - ref.cd["eps"][:, :eps.shape[1]]).max()
+    dw = np.abs(w - ref.cd["w"][:, :w.shape[1]]).max()
+    rho, pi = (np_(x) for x in ctx.density_matrix())
+    rho_o, pi_o = solve.density_on_pattern(sysm, ref.cd, mu)
+    drho, dpi = np.abs(rho - rho_o).max(), np.abs(pi - pi_o).max()
+    E_o, A_o, _, _ = solve.energies(sysm, ref.cd, mu)
+    e_all, w_all = solve.valid_terms(ref.cd)
+    dN = abs(fermi.electron_count(mu, e_all, w_all, s.kT) - s.n_electrons)
+    n = s.n_atoms
+    log(f"[config2 all {4 * n} columns] |d eps| {deps:.2e} |d w| {dw:.2e} |d rho| {drho:.2e} "
+        f"|d pi| {dpi:.2e} |dE|/atom {abs(E - E_o) / n:.2e} |dA|/atom {abs(A - A_o) / n:.2e} "
+        f"|N_oracle(mu_gpu) - Ne| {dN:.2e}")
+    assert deps <= 1e-9 and dw <= 1e-10
+    assert drho <= RHO_TOL and dpi <= 10 * RHO_TOL
+    assert abs(E - E_o) / n <= E_TOL and abs(A - A_o) / n <= E_TOL
+    assert dN <= 1e-9
+    assert abs(float(sysm.H.data @ rho) - E) <= 1e-9 * abs(E)
 
 
 @pytest.mark.parametrize("nu", [12, 20, 30, 40, 48])
-def test_sampled_columns_at_full_size_void_cell(nu):
-    # the 16x16x16 void cell: clusters from 61 to 164 atoms, so several
-    # workgroup shapes run in one pass (two rows per thread at nu = 40); a
-    # sample of columns (smallest, largest and random clusters) against the oracle
-    from oracle import krylov, neighbors
+def test_void_cell_stratified_sample(nu):
+    """The 16x16x16 void cell (clusters of 61 to 164 atoms, several workgroup
+    shapes in one pass): a 2,048-column sample stratified by cluster size
+    (eight bands of 64 atoms, all four columns of each) against the oracle."""
     import gen
+    from oracle import solve
+    from gpu_helpers import sampled_parity, stratified_atoms
     s = gen.make(3, nu=nu)
     log(f"[config3 nu {nu}] {s.n_atoms} atoms")
     ctx = gpu_context(s)
     mu, E, A = ctx.solve(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
     st = ctx.stats()
-    log(f"[config3 nu {nu}] buckets {st['krylov_buckets']} autotune {st['autotune_ms']:.1f} ms")
-    eps, w, nu_eff = (np_(x) for x in ctx.spectra())
-    rho, _ = (np_(x) for x in ctx.density_matrix())
-    rowptr = np_(ctx._csr[0])
-    colind = np_(ctx._csr[1])
-    ptr, atoms = (np_(x) for x in ctx.get_clusters())
+    ptr, _ = (np_(x) for x in ctx.get_clusters())
     sizes = np.diff(ptr)
-    rng = np.random.default_rng(11 + nu)
-    atoms_pick = np.unique(np.concatenate([np.argsort(sizes)[:4], np.argsort(sizes)[-3:],
-                                           rng.choice(s.n_atoms, 6, replace=False)]))
-    worst = 0.0
-    for J in atoms_pick:
-        clus = neighbors.cluster_of(s.pos, s.cell, int(J), s.r_cluster)
-        np.testing.assert_array_equal(clus, atoms[ptr[J]:ptr[J + 1]])
-        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
-        jl = int(np.searchsorted(clus, J))
-        for a in range(4):
-            j = 4 * int(J) + a
-            res = krylov.column_mode_k(Hc, Sc, 4 * jl + a, s.nu)
-            assert res.nu_eff == nu_eff[j]
-            np.testing.assert_allclose(eps[j, :res.nu_eff], res.eps, rtol=0, atol=1e-9)
-            np.testing.assert_allclose(w[j, :res.nu_eff], res.w, rtol=0, atol=1e-10)
-            col, _ = krylov.density_column(res, mu, s.kT)
-            lo, hi = rowptr[j], rowptr[j + 1]
-            rows = np.searchsorted(clus, colind[lo:hi] // 4) * 4 + colind[lo:hi] % 4
-            worst = max(worst, np.abs(rho[lo:hi] - col[rows]).max())
-    log(f"[config3 nu {nu}] sampled {len(atoms_pick)} atoms (sizes {sizes.min()}-{sizes.max()}), "
-        f"max |d rho| {worst:.3e}")
-    assert worst <= RHO_TOL
-    sums = np.where(np.arange(w.shape[1])[None, :] < nu_eff[:, None], w, 0.0).sum(axis=1)
+    pick = stratified_atoms(sizes, 512, strata=8, seed=11 + nu)
+    r = sampled_parity(ctx, solve.geometry(s), pick, mu, s.kT)
+    log(f"[config3 nu {nu}] buckets {st['krylov_buckets']} autotune {st['autotune_ms']:.1f} ms; "
+        f"{r['cols'].size} columns (cluster sizes {sizes[pick].min()}-{sizes[pick].max()}): "
+        f"|d eps| {r['deps']:.2e} |d w| {r['dw']:.2e} |d rho| {r['drho']:.2e} "
+        f"|d n_j| {np.abs(r['n_gpu'] - r['n_ora']).max():.2e}")
+    assert r["cols"].size >= 2048 and r["nu_mismatch"] == 0
+    assert r["deps"] <= 1e-9 and r["dw"] <= 1e-10
+    assert r["drho"] <= RHO_TOL and r["dpi"] <= 10 * RHO_TOL
+    eps_d, w_d, nu_d = ctx.spectra()
+    mask = (np.arange(w_d.shape[1])[None, :] < np_(nu_d)[:, None])
+    sums = np.where(mask, np_(w_d), 0.0).sum(axis=1)
     np.testing.assert_allclose(sums, 2.0, atol=1e-11)
     assert abs(ctx.energy()["N"] - s.n_electrons) < 1e-9
 
 
-def test_sampled_columns_at_full_size_million_site_cell():
-    # the 64x64x32 cell (voids and 3% vacancies, 915k atoms, 3.66M columns):
-    # the full forward and force backward on the GPU (Krylov columns recomputed
-    # in pass 2, scratch in chunks), a sample of columns against the oracle one
-    # by one, and invariants at full size
+def test_million_site_cell_stratified_sample():
+    """The 64x64x32 cell (voids and 3% vacancies, 915k atoms, 3.66M columns):
+    forward and force backward at full size (Krylov columns recomputed in
+    pass 2), a 4,096-column sample stratified by cluster size against the
+    oracle, invariants of every column.
+
+    Electron count: |N(mu) - N_e| is a sum of 1.1e8 terms of N_e = 3.66e6
+    total, so its rounding alone is a few eps N_e log2(terms) (about 1e-8);
+    the bar is 4 eps N_e log2(terms).  The oracle's residual at the GPU's mu
+    is estimated from the sample: N_gpu - N_e plus M times the mean
+    per-column difference n_j(oracle) - n_j(gpu), and held to the same bar."""
     import time
     import torch
-    from oracle import krylov, neighbors
-    from paper_1210_1531_amd import model
     import gen
+    from oracle import solve
+    from paper_1210_1531_amd import model
+    from gpu_helpers import sampled_parity, stratified_atoms
     s = gen.make(5)
+    M = 4 * s.n_atoms
     log(f"[config5] {s.n_atoms} atoms")
     ctx = gpu_context(s)
     torch.cuda.synchronize()
@@ -298,7 +279,7 @@ def test_sampled_columns_at_full_size_million_site_cell():
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     st = ctx.stats()
-    log(f"[config5] forward {t_fwd:.2f} s ({4 * s.n_atoms / t_fwd:.3e} columns/s), "
+    log(f"[config5] forward {t_fwd:.2f} s ({M / t_fwd:.3e} columns/s), "
         f"workflow {st['workflow_used']}, device bytes {st['device_bytes'] / 1e9:.1f} GB")
     F = ctx.forces(model.sk_model())
     assert torch.isfinite(F).all()
@@ -306,41 +287,26 @@ def test_sampled_columns_at_full_size_million_site_cell():
     log(f"[config5] |sum F| {fsum:.3e}, max |F| {F.abs().max().item():.3e}")
     assert fsum < 1e-6
     eps_d, w_d, nu_d = ctx.spectra()
-    rho_d, _ = ctx.density_matrix()
-    # closure of every column's weights, electron count
     mask = torch.arange(w_d.shape[1], device=w_d.device)[None, :] < nu_d[:, None].long()
     sums = torch.where(mask, w_d, torch.zeros_like(w_d)).sum(dim=1)
     assert (sums - 2.0).abs().max().item() < 1e-11
-    dN = abs(ctx.energy()["N"] - s.n_electrons)
-    log(f"[config5] |N - Ne| {dN:.3e}")
-    assert dN < 1e-6
-    rowptr = np_(ctx._csr[0])
-    colind_d = ctx._csr[1]
-    ptr, atoms = (np_(x) for x in ctx.get_clusters())
+    terms = int(mask.sum().item())
+    bar = 4 * np.finfo(np.float64).eps * s.n_electrons * np.log2(terms)
+    dN_gpu = ctx.energy()["N"] - s.n_electrons
+    ptr, _ = (np_(x) for x in ctx.get_clusters())
     sizes = np.diff(ptr)
-    rng = np.random.default_rng(5)
-    atoms_pick = np.unique(np.concatenate([np.argsort(sizes)[:2], np.argsort(sizes)[-2:],
-                                           rng.choice(s.n_atoms, 4, replace=False)]))
-    worst = 0.0
-    for J in atoms_pick:
-        clus = neighbors.cluster_of(s.pos, s.cell, int(J), s.r_cluster)
-        np.testing.assert_array_equal(clus, atoms[ptr[J]:ptr[J + 1]])
-        Hc, Sc = neighbors.cluster_matrices(s.pos, s.cell, clus)
-        jl = int(np.searchsorted(clus, J))
-        for a in range(4):
-            j = 4 * int(J) + a
-            res = krylov.column_mode_k(Hc, Sc, 4 * jl + a, s.nu)
-            assert res.nu_eff == int(nu_d[j])
-            np.testing.assert_allclose(np_(eps_d[j])[:res.nu_eff], res.eps, rtol=0, atol=1e-9)
-            np.testing.assert_allclose(np_(w_d[j])[:res.nu_eff], res.w, rtol=0, atol=1e-10)
-            col, _ = krylov.density_column(res, mu, s.kT)
-            lo, hi = int(rowptr[j]), int(rowptr[j + 1])
-            ci = np_(colind_d[lo:hi])
-            rows = np.searchsorted(clus, ci // 4) * 4 + ci % 4
-            worst = max(worst, np.abs(np_(rho_d[lo:hi]) - col[rows]).max())
-    log(f"[config5] sampled {len(atoms_pick)} atoms (sizes {sizes.min()}-{sizes.max()}), "
-        f"max |d rho| {worst:.3e}")
-    assert worst <= RHO_TOL
+    pick = stratified_atoms(sizes, 1024, strata=8, seed=5)
+    r = sampled_parity(ctx, solve.geometry(s), pick, mu, s.kT)
+    dn = r["n_ora"] - r["n_gpu"]
+    est = dN_gpu + M * float(np.mean(dn))
+    log(f"[config5] {r['cols'].size} columns (cluster sizes {sizes[pick].min()}-{sizes[pick].max()}): "
+        f"|d eps| {r['deps']:.2e} |d w| {r['dw']:.2e} |d rho| {r['drho']:.2e}; "
+        f"N_gpu - Ne {dN_gpu:.2e}, max |d n_j| {np.abs(dn).max():.2e}, "
+        f"estimated N_oracle(mu_gpu) - Ne {est:.2e} (bar {bar:.2e})")
+    assert r["cols"].size >= 4096 and r["nu_mismatch"] == 0
+    assert r["deps"] <= 1e-9 and r["dw"] <= 1e-10
+    assert r["drho"] <= RHO_TOL and r["dpi"] <= 10 * RHO_TOL
+    assert abs(dN_gpu) <= bar and abs(est) <= bar
 
 
 # |d B| <= 16 |H|max |d rho|: the rho bar times sixteen entries of at most 6 eV
