@@ -82,44 +82,98 @@ def column_gradient(Hc, Sc, l, nu, mu, kT):
     return float(om.detach()), H.grad.numpy(), S.grad.numpy()
 
 
-def exact_forces(sysm, mu, cols=None):
-    """F_I = -dOmega/dR_I at fixed mu, summed over the given columns (all if
-    None): the exact derivative of the truncated-Krylov free energy.
+def atom_force_parts(sysm, J, mu, alphas=(0, 1, 2, 3)):
+    """The contribution of the columns (J, alpha) to -dOmega/dR of every atom
+    of J's cluster: (cluster atoms, parts of shape (atoms, 3)).
 
     Each column's gradient with respect to its cluster's H_C and S_C is
     contracted with the Slater-Koster block derivatives of every pair of
     cluster atoms closer than r_cut (the blocks H_AB(d), d = R_B - R_A, so
-    dH_AB/dR_B = +dH/dd and dH_AB/dR_A = -dH/dd).
+    dH_AB/dR_B = +dH/dd and dH_AB/dR_A = -dH/dd).  sysm: a System or a
+    Geometry (positions, box, cluster radius, nu, kT, model).
     """
+    p = sysm.params
+    atoms = _nb.cluster_of(sysm.pos, sysm.cell, J, sysm.r_cluster)
+    Hc, Sc = _nb.cluster_matrices(sysm.pos, sysm.cell, atoms, p)
+    jl = int(np.searchsorted(atoms, J))
+    gH = np.zeros_like(Hc)
+    gS = np.zeros_like(Sc)
+    for a in alphas:
+        _, h, s = column_gradient(Hc, Sc, NORB * jl + a, sysm.nu, mu, sysm.kT)
+        gH += h
+        gS += s
+    dOm = np.zeros((atoms.size, 3))
+    P = sysm.pos[atoms]
+    for A in range(atoms.size):
+        d_all = _nb.min_image(P - P[A][None, :], sysm.cell[None, :])
+        r2 = np.einsum("ij,ij->i", d_all, d_all)
+        for B in np.nonzero(r2 < p.r_cut * p.r_cut)[0]:
+            if B == A:
+                continue
+            dH, dS = _sk.pair_block_grads(d_all[B], p)  # (3, 4, 4) each, d/dd
+            blkH = gH[NORB * A:NORB * A + NORB, NORB * B:NORB * B + NORB]
+            blkS = gS[NORB * A:NORB * A + NORB, NORB * B:NORB * B + NORB]
+            gvec = np.einsum("cab,ab->c", dH, blkH) + np.einsum("cab,ab->c", dS, blkS)
+            dOm[B] += gvec
+            dOm[A] -= gvec
+    return atoms, -dOm
+
+
+def exact_forces(sysm, mu, cols=None):
+    """F_I = -dOmega/dR_I at fixed mu, summed over the given columns (all if
+    None): the exact derivative of the truncated-Krylov free energy."""
     n = sysm.n_atoms
     cols = np.arange(NORB * n) if cols is None else np.asarray(cols)
-    dOm = np.zeros((n, 3))
+    F = np.zeros((n, 3))
     by_atom = {}
     for j in cols:
         by_atom.setdefault(int(j) // NORB, []).append(int(j) % NORB)
-    p = sysm.params
     for J, alphas in sorted(by_atom.items()):
-        atoms = _nb.cluster_of(sysm.pos, sysm.cell, J, sysm.r_cluster)
-        Hc, Sc = _nb.cluster_matrices(sysm.pos, sysm.cell, atoms, p)
-        jl = int(np.searchsorted(atoms, J))
-        gH = np.zeros_like(Hc)
-        gS = np.zeros_like(Sc)
-        for a in alphas:
-            _, h, s = column_gradient(Hc, Sc, NORB * jl + a, sysm.nu, mu, sysm.kT)
-            gH += h
-            gS += s
-        P = sysm.pos[atoms]
-        for A in range(atoms.size):
-            d_all = _nb.min_image(P - P[A][None, :], sysm.cell[None, :])
-            r2 = np.einsum("ij,ij->i", d_all, d_all)
-            for B in np.nonzero(r2 < p.r_cut * p.r_cut)[0]:
-                if B == A:
-                    continue
-                dH, dS = _sk.pair_block_grads(d_all[B], p)  # (3, 4, 4) each, d/dd
-                blkH = gH[NORB * A:NORB * A + NORB, NORB * B:NORB * B + NORB]
-                blkS = gS[NORB * A:NORB * A + NORB, NORB * B:NORB * B + NORB]
-                gvec = np.einsum("cab,ab->c", dH, blkH) + np.einsum("cab,ab->c", dS, blkS)
-                dOm[atoms[B]] += gvec
-                dOm[atoms[A]] -= gvec
-    return -dOm
+        atoms, parts = atom_force_parts(sysm, J, mu, alphas)
+        F[atoms] += parts
+    return F
 
+
+_WORK = {}
+
+
+def _init_worker(geo, mu):
+    torch.set_num_threads(1)
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover - threadpoolctl is optional
+        pass
+    _WORK["geo"] = geo
+    _WORK["mu"] = mu
+
+
+def _parts_task(J):
+    atoms, parts = atom_force_parts(_WORK["geo"], J, _WORK["mu"])
+    return J, atoms, parts
+
+
+def exact_forces_on(geo, targets, mu, workers=None):
+    """Exact forces of the atoms `targets` only: every atom whose cluster
+    holds a target contributes (the cluster relation is symmetric, so these
+    are the atoms of the targets' own clusters), spread over fork-server
+    workers.  Returns an array (len(targets), 3)."""
+    from . import pool as _pool
+    targets = np.asarray(targets, dtype=np.int64)
+    need = np.unique(np.concatenate(
+        [_nb.cluster_of(geo.pos, geo.cell, int(I), geo.r_cluster) for I in targets]))
+    workers = workers or _pool.default_workers()
+    if workers > 1 and need.size > 8:
+        with _pool.executor(workers, initializer=_init_worker, initargs=(geo, mu)) as ex:
+            res = list(ex.map(_parts_task, need.tolist(),
+                              chunksize=max(1, need.size // (8 * workers))))
+    else:
+        res = [(int(J), *atom_force_parts(geo, int(J), mu)) for J in need]
+    where = {int(I): i for i, I in enumerate(targets)}
+    F = np.zeros((targets.size, 3))
+    for J, atoms, parts in sorted(res, key=lambda t: t[0]):
+        for a, I in enumerate(atoms):
+            i = where.get(int(I))
+            if i is not None:
+                F[i] += parts[a]
+    return F

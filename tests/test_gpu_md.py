@@ -70,8 +70,7 @@ def test_md_frames_match_oracle_mini_vac():
                                  phi0=PHI0, m_rep=MREP, r_cluster=s.r_cluster, nu=s.nu,
                                  kT=s.kT, n_electrons=s.n_electrons)
     pos, vel, F = np_(pos), np_(vel), np_(F)
-    workers = min(16, os.cpu_count() or 1)
-    fr = md.velocity_verlet(s.pos, v0, s.cell, md.krylov_forces(s, workers=workers, phi0=PHI0),
+    fr = md.velocity_verlet(s.pos, v0, s.cell, md.krylov_forces(s, phi0=PHI0),
                             MASS, dt, steps)
     n = s.n_atoms
     dx = np.abs(_min_image(pos - fr[-1].pos, s.cell)).max()

@@ -66,3 +66,12 @@ def test_exact_forces_match_differences_of_the_free_energy(tiny):
         assert abs(Fx[I, c] - fd) < 1e-5
         assert abs(r.F[I, c] - fd) > 0.1  # the Hellmann-Feynman reading is not the gradient here
     assert np.abs(Fx.sum(axis=0)).max() < 1e-9  # translation invariance
+
+
+def test_forces_of_selected_atoms_equal_the_full_sum(tiny):
+    # the pooled driver over the clusters that hold the chosen atoms gives
+    # the same forces as the sum over every column
+    s, sysm, r, Fx = tiny
+    pick = np.array([0, 17, 40])
+    Fp = adjoint.exact_forces_on(so.geometry(s), pick, r.mu, workers=4)
+    np.testing.assert_allclose(Fp, Fx[pick], rtol=0, atol=1e-12)
