@@ -291,6 +291,24 @@ int mag_backward(mag_ctx* ctx, double gA, double* dAdH_csr, double* dAdS_csr,
  * layout of mag_sk_build. */
 int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind);
 
+/* Exact forces of the truncated-Krylov method: F_I = -dOmega/dR_I at the
+ * last solve's mu, Omega = sum_j Omega_j, Omega_j = sum_k w_jk omega(eps_jk)
+ * with omega(e) = -kT ln(1 + exp(-(e - mu)/kT)) (the grand potential; at
+ * fixed electron number its position gradient is that of A_free).  The force
+ * through rho and pi (mag_forces; the letter takes energy and force through
+ * the density matrix, after Eq. 1) is this derivative only when every
+ * column's Krylov space is exact; here each column is differentiated through
+ * its Krylov space as well: its Ritz data give dOmega_j/dh and dOmega_j/ds of
+ * the projected pencil (divided differences of omega), the Krylov recurrence
+ * is run backwards with the basis recomputed (no basis is stored), and the
+ * resulting dOmega_j/dH_C, dOmega_j/dS_C are contracted with the Slater-Koster
+ * derivatives of `model` on the cluster's pairs.  A column whose Krylov space
+ * is invariant before nu is differentiated at its dimension.  F: n_atoms x 3
+ * (mem_kind).  Requires a solve, mag_system.pos and the pattern of
+ * mag_sk_build; supports nu <= 30.  Errors: MAG_ESTATE before a solve,
+ * MAG_EINVAL (model, F, no positions), MAG_EUNSUPPORTED (nu > 30). */
+int mag_forces_exact(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind);
+
 /* Integrated crystal orbital Hamiltonian populations (Eqs. 4-8) of the last
  * solve, one value per 4x4 block of the pattern, in block-CSR order (block t
  * of block row J, whose column atom K is the t-th atom of row J's CSR
@@ -412,6 +430,7 @@ typedef struct {
   double t_cohp_ms;        /* last mag_cohp */
   double t_md_step_ms;     /* last mag_md_run: average wall time of one step */
   double t_cocg_ms;        /* last mag_cocg_columns (its kernels) */
+  double t_forces_exact_ms; /* last mag_forces_exact */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

@@ -106,6 +106,7 @@ def _block_row(geo, J):
 def _atom_columns(args):
     J, alphas, pat_atoms, mode, full = args
     geo = _WORK["geo"]
+    breakdown = _WORK.get("breakdown", _kry.BREAKDOWN)
     atoms = _nb.cluster_of(geo.pos, geo.cell, J, geo.r_cluster)
     Hc, Sc = _nb.cluster_matrices(geo.pos, geo.cell, atoms, geo.params)
     jl = int(np.searchsorted(atoms, J))
@@ -117,7 +118,7 @@ def _atom_columns(args):
     for a in alphas:
         l = NORB * jl + a
         if mode == "K":
-            res = _kry.column_mode_k(Hc, Sc, l, geo.nu)
+            res = _kry.column_mode_k(Hc, Sc, l, geo.nu, breakdown=breakdown)
         else:
             res = _kry.column_mode_d(Hc, Sc, l)
         ypd = res.Y[pat_rows, :] * res.d[None, :]
@@ -130,24 +131,28 @@ def _atom_columns(args):
     return out
 
 
-def _init_worker(geo):
+def _init_worker(geo, breakdown=_kry.BREAKDOWN):
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:  # pragma: no cover - threadpoolctl is optional
         pass
     _WORK["geo"] = geo
+    _WORK["breakdown"] = breakdown
 
 
-def column_data(sysm, cols=None, mode="K", workers=None, full=False):
+def column_data(sysm, cols=None, mode="K", workers=None, full=False, breakdown=None):
     """Ritz data for the given global columns (all if None).
 
     sysm: a System or a Geometry.  Returns a dict with arrays eps, w (ncols x
     width, zero-padded), nu_eff, the column ids, and per-column lists ypd
     (pattern rows x nu_eff) and, if ``full``, the full Ritz vectors and
     cluster atoms.  With workers > 1 the atoms are spread over fork-server
-    processes (oracle.pool); a worker that dies raises.
+    processes (oracle.pool); a worker that dies raises.  breakdown: the
+    relative residual below which a Krylov space counts as invariant
+    (default krylov.BREAKDOWN).
     """
+    breakdown = _kry.BREAKDOWN if breakdown is None else float(breakdown)
     M = sysm.M
     cols = np.arange(M) if cols is None else np.asarray(cols, dtype=np.int64)
     by_atom = {}
@@ -160,16 +165,18 @@ def column_data(sysm, cols=None, mode="K", workers=None, full=False):
                    params=sysm.params)
     workers = workers or _pool.default_workers()
     if workers > 1 and len(tasks) > 8:
-        with _pool.executor(workers, initializer=_init_worker, initargs=(geo,)) as ex:
+        with _pool.executor(workers, initializer=_init_worker, initargs=(geo, breakdown)) as ex:
             chunks = list(ex.map(_atom_columns, tasks,
                                  chunksize=max(1, len(tasks) // (8 * workers))))
     else:
-        saved = _WORK.get("geo")
+        saved = dict(_WORK)
         _WORK["geo"] = geo
+        _WORK["breakdown"] = breakdown
         try:
             chunks = [_atom_columns(t) for t in tasks]
         finally:
-            _WORK["geo"] = saved
+            _WORK.clear()
+            _WORK.update(saved)
     items = {it["j"]: it for ch in chunks for it in ch}
     width = max([it["eps"].size for it in items.values()] + [1])
     n = cols.size
@@ -330,9 +337,10 @@ class Result:
     F: np.ndarray = None
 
 
-def solve(sysm: System, mode="K", workers=None, with_forces=False, mu=None) -> Result:
+def solve(sysm: System, mode="K", workers=None, with_forces=False, mu=None,
+          breakdown=None) -> Result:
     """Full forward (and optionally forces) over every column."""
-    cd = column_data(sysm, None, mode=mode, workers=workers)
+    cd = column_data(sysm, None, mode=mode, workers=workers, breakdown=breakdown)
     if mu is None:
         mu = chemical_potential(sysm, cd)
     E, A, S_ent, N = energies(sysm, cd, mu)

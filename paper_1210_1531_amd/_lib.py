@@ -108,6 +108,7 @@ class MagStats(C.Structure):
         ("t_cohp_ms", C.c_double),
         ("t_md_step_ms", C.c_double),
         ("t_cocg_ms", C.c_double),
+        ("t_forces_exact_ms", C.c_double),
     ]
 
 
@@ -140,6 +141,7 @@ PROTOTYPES = {
     "mag_green_columns": (I, [CTX, C.POINTER(MagOpts), P, I64, P, I, P, P, I]),
     "mag_backward": (I, [CTX, D, P, P, I]),
     "mag_forces": (I, [CTX, C.POINTER(MagSKModel), P, I]),
+    "mag_forces_exact": (I, [CTX, C.POINTER(MagSKModel), P, I]),
     "mag_icohp": (I, [CTX, C.POINTER(MagSKModel), P, P, P, I]),
     "mag_cohp": (I, [CTX, C.POINTER(D), I, D, P, I]),
     "mag_cocg_columns": (I, [CTX, P, I64, P, I, D, I, P, P, P, I]),

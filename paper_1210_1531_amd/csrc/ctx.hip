@@ -198,6 +198,9 @@ struct ColumnJob {
   double* out = nullptr;
   const double* z = nullptr;         // consumer 3: complex energies (device)
   int nz = 0;
+  // consumer 4: exact gradient (the chunk's Ritz vectors -> hbar, sbar ->
+  // the adjoint sweep and contraction -> per-atom force parts in adj_fJ)
+  SKModelDev skm{};
 };
 
 // split slots [0, n) of a column list into KRYLOV_QUEUES contiguous ranges of
@@ -229,11 +232,13 @@ int64_t chunk_columns(const ColumnJob& job, int64_t n) {
       sizeof(double) * ((size_t)2 * cap * cap + cap + (size_t)pat_stride * cap) + 2 * sizeof(int32_t) +
       sizeof(double) * ((size_t)5 * cap + 2 * (size_t)rec_cap) +
       sizeof(int32_t) * ((size_t)sweep_cap + 2) +
-      (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0);
+      (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0) +
+      (job.consumer == 4 ? sizeof(double) * ((size_t)3 * cap * cap + 3 * cap) : 0);
   const char* env = std::getenv("MAG_SCRATCH_GB");
   const double budget_gb = env ? std::atof(env) : 8.0;
   int64_t bmax = (int64_t)(budget_gb * 1e9 / (double)per_slot);
-  if (bmax < 1) bmax = 1;
+  if (job.consumer == 4) bmax -= bmax % NORB;  // whole atoms per chunk
+  if (bmax < NORB) bmax = NORB;
   return std::min(n, bmax);
 }
 
@@ -431,6 +436,11 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
   ALLOC(ctx->k_qlst, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_fbl, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_fbc, sizeof(int32_t));
+  if (job.consumer == 4) {
+    ALLOC(ctx->adj_cvec, sizeof(double) * bsz * cap * cap);
+    ALLOC(ctx->adj_cdg, sizeof(double) * bsz * 3 * cap);
+    ALLOC(ctx->adj_hbar, sizeof(double) * bsz * 2 * cap * cap);
+  }
   double* Pbuf = job.P_store;
   if (job.want_P && !job.P_store) {
     ALLOC(ctx->tmp_out, sizeof(double) * bsz * (size_t)pat_stride * job.nu);
@@ -507,6 +517,8 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
     ea.fb_count = ctx->k_fbc.as<int32_t>();
     ea.rec_cap = rec_cap;
     ea.sweep_cap = sweep_cap;
+    ea.cvec = job.consumer == 4 ? ctx->adj_cvec.as<double>() : nullptr;
+    ea.cdg = job.consumer == 4 ? ctx->adj_cdg.as<double>() : nullptr;
 
     if (schedule == MAG_SCHED_PLAIN) {
       for (int64_t q = 0; q < cnt; ++q) {
@@ -535,6 +547,10 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
           e1.nu_eff_out = ea.nu_eff_out + q;
         }
         if (e1.P && !job.P_store) e1.P = Pbuf + q * (int64_t)pat_stride * job.nu;
+        if (e1.cvec) {
+          e1.cvec = ea.cvec + q * (int64_t)cap * cap;
+          e1.cdg = ea.cdg + q * (int64_t)3 * cap;
+        }
         HIPCHK(launch_eig(e1, ctx->stream));
       }
     } else {
@@ -615,6 +631,38 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
       }
     }
 
+    if (job.consumer == 4) {
+      HIPCHK(launch_adj_prep(ctx->adj_cvec.as<double>(), ctx->adj_cdg.as<double>(), ka.nu_eff, cnt,
+                             cap, ctx->state.as<MuState>(), ctx->adj_hbar.as<double>(),
+                             ctx->stream));
+      const int occ = std::max(1, adjoint_occupancy(cap));
+      const int64_t natoms = cnt / NORB;
+      const int grid = (int)std::min<int64_t>(natoms, (int64_t)ncu * occ);
+      ALLOC(ctx->adj_wbar, adjoint_scratch_per_wg(cap) * (size_t)grid);
+      ALLOC(ctx->adj_counter, sizeof(int32_t));
+      HIPCHK(launch_fill_i32(ctx->adj_counter.as<int32_t>(), 1, 0, ctx->stream));
+      AdjointArgs aa{};
+      aa.bptr = ka.bptr;
+      aa.bcol = ka.bcol;
+      aa.bval = ka.bval;
+      aa.clus_ptr = ka.clus_ptr;
+      aa.clus_atoms = ka.clus_atoms;
+      aa.pos = ctx->pos.as<double>();
+      for (int d = 0; d < 3; ++d) aa.box[d] = ctx->cell[d];
+      aa.m = job.skm;
+      aa.cols = ka.cols;
+      aa.natoms = natoms;
+      aa.nu = job.nu;
+      aa.breakdown = job.breakdown;
+      aa.hbar = ctx->adj_hbar.as<double>();
+      aa.nu_eff = ka.nu_eff;
+      aa.wbar = ctx->adj_wbar.as<double>();
+      aa.fJ = ctx->adj_fJ.as<double>();
+      aa.counter = ctx->adj_counter.as<int32_t>();
+      aa.err = ka.err;
+      aa.cap = cap;
+      HIPCHK(launch_adjoint(aa, grid, ctx->stream));
+    }
     if (job.consumer == 2) {
       HIPCHK(launch_cluster_rho(Pbuf, pat_stride, ka.cols, cnt, ka.npat, job.out_off + i0,
                                 job.eps + i0 * job.nu, job.nu_eff + i0, job.nu,
@@ -1713,6 +1761,48 @@ int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind)
   TRY(sync(ctx));
   ctx->stats.t_forces_ms = tm.stop_ms();
   return take_errors(ctx, "mag_forces");
+}
+
+int mag_forces_exact(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind) {
+  TRY(ensure_system(ctx));
+  TRY(check_mem_kind(ctx, mem_kind));
+  if (!model_ok(model)) return fail(ctx, MAG_EINVAL, "invalid Slater-Koster model");
+  if (!F) return fail(ctx, MAG_EINVAL, "F is NULL");
+  if (!ctx->has_pos) return fail(ctx, MAG_EINVAL, "forces need mag_system.pos");
+  if (!ctx->solved) return fail(ctx, MAG_ESTATE, "no solve: call mag_solve_columns first");
+  const int cap = krylov_capacity(ctx->nu);
+  if (!adjoint_supported(cap))
+    return fail(ctx, MAG_EUNSUPPORTED, "the exact gradient supports nu <= 30");
+  if (adjoint_occupancy(cap) < 1)
+    return fail(ctx, MAG_EUNSUPPORTED, "the exact-gradient kernel does not fit on this device");
+  Timer tm(ctx->stream);
+  ALLOC(ctx->adj_fJ, sizeof(double) * 3 * std::max<int64_t>(ctx->clus_total, 1));
+  ALLOC(ctx->adj_F, sizeof(double) * 3 * ctx->N);
+  ColumnJob job;
+  job.cols_dev = ctx->k_cols.as<int32_t>();
+  job.cols_host = ctx->h_order;
+  job.nu = ctx->nu;
+  job.breakdown = ctx->opts.breakdown > 0 ? ctx->opts.breakdown : 1e-12;
+  job.schedule = MAG_SCHED_PERSISTENT;
+  // the first pass's spectra stay as they are: this pass writes scratch rows
+  ALLOC(ctx->tmp_cols, sizeof(double) * 2 * ctx->M * ctx->nu + sizeof(int32_t) * ctx->M);
+  job.eps = ctx->tmp_cols.as<double>();
+  job.w = job.eps + ctx->M * ctx->nu;
+  job.nu_eff = reinterpret_cast<int32_t*>(job.w + ctx->M * ctx->nu);
+  job.consumer = 4;
+  job.skm = to_dev(*model);
+  const mag_stats keep = ctx->stats;  // the pass-1 timings stay the solve's
+  TRY(run_columns(ctx, job));
+  ctx->stats.t_krylov_ms = keep.t_krylov_ms;
+  ctx->stats.t_eig_ms = keep.t_eig_ms;
+  ctx->stats.krylov_launches = keep.krylov_launches;
+  ctx->stats.schedule_used = keep.schedule_used;
+  HIPCHK(launch_gather_forces(ctx->clus_ptr.as<int64_t>(), ctx->clus_atoms.as<int32_t>(), ctx->N,
+                              ctx->adj_fJ.as<double>(), ctx->adj_F.as<double>(), ctx->stream));
+  TRY(copy_out(ctx, F, ctx->adj_F.p, sizeof(double) * 3 * ctx->N, mem_kind));
+  TRY(sync(ctx));
+  ctx->stats.t_forces_exact_ms = tm.stop_ms();
+  return take_errors(ctx, "mag_forces_exact");
 }
 
 int mag_icohp(mag_ctx* ctx, const mag_sk_model* model, double* B, double* B_sigma,

@@ -544,6 +544,15 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
     gk = fma(s0[t], y[t], gk);
   }
   const double wk = G_SPIN * dk * gk;
+  if (a.cvec && lane < NM) {
+    double* cv = a.cvec + slot * (int64_t)(NM * NM) + lane * NM;
+#pragma unroll
+    for (int t = 0; t < NM; ++t) cv[t] = (lane < n && t < n) ? y[t] : 0.0;
+    double* cd = a.cdg + slot * (int64_t)(3 * NM);
+    cd[lane] = (lane < n) ? ek : 0.0;
+    cd[NM + lane] = (lane < n) ? dk : 0.0;
+    cd[2 * NM + lane] = (lane < n) ? gk : 0.0;
+  }
   if (lane < n) {
     if (!isfinite(ek) || !isfinite(wk)) atomicOr(a.err, (int)KERR_NONFINITE);
     a.eps[oi * nuo + rank] = ek;

@@ -151,6 +151,11 @@ struct EigArgs {
   int32_t* fb_count;          // 1
   int rec_cap;
   int sweep_cap;
+  // exact gradient (optional): the Ritz vectors c (per slot cap x cap, vector
+  // k at k * cap) and (eigenvalue, d, g) of each (per slot 3 x cap), in the
+  // solver's own order
+  double* cvec;
+  double* cdg;
 };
 
 struct DensityArgs {
@@ -182,6 +187,7 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t s);
 int eig_rec_cap(int cap);
 int eig_sweep_cap(int cap);
 hipError_t launch_density(const DensityArgs& a, hipStream_t s);
+
 
 hipError_t launch_mu_setup(MuState* st, double ne, double kT, double tol, double mu_fixed,
                            int fixed, hipStream_t s);
@@ -219,6 +225,40 @@ struct SKModelDev {
   double vs[4];  // same for S - I
   double r0, r_on, r_cut;
 };
+// exact gradient of the truncated-Krylov grand potential (adjoint.hip)
+constexpr int ADJ_KC = 4;  // basis columns staged per contraction pass
+struct AdjointArgs {
+  const int32_t* bptr;
+  const int32_t* bcol;
+  const double* bval;
+  const int64_t* clus_ptr;
+  const int32_t* clus_atoms;
+  const double* pos;       // N x 3
+  double box[3];
+  SKModelDev m;
+  const int32_t* cols;     // columns of the chunk in slot order, the four of an atom together
+  int64_t natoms;          // atoms of the chunk (slots 4 a .. 4 a + 3)
+  int nu;
+  double breakdown;
+  const double* hbar;      // per slot: hbar (cap x cap) then sbar
+  const int32_t* nu_eff;   // per slot, from the first pass over the chunk
+  double* wbar;            // per workgroup: nu x (rows) scratch
+  double* fJ;              // per atom J: its parts for its cluster atoms, at 3 clus_ptr[J]
+  int32_t* counter;        // atom counter of the persistent workgroups
+  int32_t* err;
+  int cap;
+};
+int adjoint_supported(int cap);
+size_t adjoint_dyn_lds(int cap);
+size_t adjoint_scratch_per_wg(int cap);
+int adjoint_occupancy(int cap);
+hipError_t launch_adjoint(const AdjointArgs& a, int grid, hipStream_t s);
+hipError_t launch_adj_prep(const double* cvec, const double* cdg, const int32_t* nu_eff,
+                           int64_t ncols, int cap, const MuState* st, double* hbar, hipStream_t s);
+hipError_t launch_gather_forces(const int64_t* clus_ptr, const int32_t* clus_atoms, int64_t n,
+                                const double* fJ, double* F, hipStream_t s);
+
+
 hipError_t launch_sk_count(const double* pos, int64_t n, const double cell[3], double rc,
                            const CellList& cl, int32_t* cnt, int32_t* err, hipStream_t s);
 hipError_t launch_sk_fill(const double* pos, int64_t n, const double cell[3], double rc,
@@ -309,6 +349,7 @@ struct mag_ctx {
   mag::DevBuf sk_pos, sk_bptr, sk_bcol, sk_rowptr, sk_colind, sk_H, sk_S;
   mag::DevBuf md_x, md_v, md_F, md_Frep, md_e, md_sum;  // MD step state
   mag::DevBuf f_part, f_grad;  // force contraction: per-block parts, per-atom sums
+  mag::DevBuf adj_cvec, adj_cdg, adj_hbar, adj_wbar, adj_fJ, adj_F, adj_counter;  // exact gradient
 
   // system
   bool has_system = false;

@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "mag_internal.h"
+#include "sk_dev.h"
 
 namespace mag {
 
@@ -15,16 +16,6 @@ constexpr int STPB = 128;
 // ---------------------------------------------------------------------------
 // geometry helpers
 // ---------------------------------------------------------------------------
-struct Box {
-  double L[3];
-};
-
-__device__ __forceinline__ void min_image(const Box& b, double& dx, double& dy, double& dz) {
-  dx -= b.L[0] * rint(dx / b.L[0]);
-  dy -= b.L[1] * rint(dy / b.L[1]);
-  dz -= b.L[2] * rint(dz / b.L[2]);
-}
-
 struct CellView {
   int nc[3];
   int brute;
@@ -193,81 +184,6 @@ __global__ void sk_csr_kernel(const int32_t* bptr, const int32_t* bcol, int64_t 
       for (int be = 0; be < NORB; ++be) colind[r0 + 4 * t + be] = NORB * bcol[b0 + t] + be;
   }
   if (J == n - 1) rowptr[NORB * n] = 16 * (int64_t)bptr[n];
-}
-
-// ---------------------------------------------------------------------------
-// two-center blocks and their derivatives
-// ---------------------------------------------------------------------------
-// quintic smooth step from 1 at r_on to 0 at r_cut, and its derivative
-__device__ __forceinline__ void smooth_cutoff(const SKModelDev& m, double r, double& fc,
-                                              double& dfc) {
-  const double width = m.r_cut - m.r_on;
-  const double t = (r - m.r_on) / width;
-  if (t <= 0.0) {
-    fc = 1.0;
-    dfc = 0.0;
-  } else if (t >= 1.0) {
-    fc = 0.0;
-    dfc = 0.0;
-  } else {
-    const double t2 = t * t, t3 = t2 * t;
-    fc = 1.0 - (10.0 * t3 - 15.0 * t3 * t + 6.0 * t3 * t2);
-    dfc = -(30.0 * t2 - 60.0 * t3 + 30.0 * t3 * t) / width;
-  }
-}
-
-__device__ __forceinline__ void radial(const SKModelDev& m, double r, double& u, double& du) {
-  double fc, dfc;
-  smooth_cutoff(m, r, fc, dfc);
-  const double g = (m.r0 / r) * (m.r0 / r);
-  const double dg = -2.0 * m.r0 * m.r0 / (r * r * r);
-  u = g * fc;
-  du = dg * fc + g * dfc;
-}
-
-// B (4x4) for displacement d from the row atom to the column atom
-__device__ __forceinline__ void two_center(const SKModelDev& m, const double* V, double dx,
-                                           double dy, double dz, double B[4][4]) {
-  const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  const double l[3] = {dx / r, dy / r, dz / r};
-  double u, du;
-  radial(m, r, u, du);
-  B[0][0] = V[0] * u;
-  for (int a = 0; a < 3; ++a) {
-    B[0][1 + a] = l[a] * V[1] * u;
-    B[1 + a][0] = -l[a] * V[1] * u;
-    for (int b = 0; b < 3; ++b) {
-      const double ll = l[a] * l[b];
-      B[1 + a][1 + b] = (ll * V[2] + ((a == b ? 1.0 : 0.0) - ll) * V[3]) * u;
-    }
-  }
-}
-
-// sum_ab G[a][b] dB_ab/dd  (3-vector), for weights G on the block
-__device__ __forceinline__ void two_center_contract(const SKModelDev& m, const double* V,
-                                                    double dx, double dy, double dz,
-                                                    const double G[4][4], double out[3]) {
-  const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  const double l[3] = {dx / r, dy / r, dz / r};
-  double u, du;
-  radial(m, r, u, du);
-  for (int c = 0; c < 3; ++c) {
-    const double dr = l[c];
-    double acc = G[0][0] * V[0] * du * dr;
-    for (int a = 0; a < 3; ++a) {
-      const double dla = ((a == c ? 1.0 : 0.0) - l[a] * l[c]) / r;
-      const double sp = dla * V[1] * u + l[a] * V[1] * du * dr;
-      acc += G[0][1 + a] * sp - G[1 + a][0] * sp;
-      for (int b = 0; b < 3; ++b) {
-        const double dlb = ((b == c ? 1.0 : 0.0) - l[b] * l[c]) / r;
-        const double ll = l[a] * l[b];
-        const double ang = ll * V[2] + ((a == b ? 1.0 : 0.0) - ll) * V[3];
-        const double dang = (dla * l[b] + l[a] * dlb) * (V[2] - V[3]);
-        acc += G[1 + a][1 + b] * (dang * u + ang * du * dr);
-      }
-    }
-    out[c] = acc;
-  }
 }
 
 // the same block split by bond type: sigma (V_ss, V_sp, V_pp sigma terms)

@@ -305,6 +305,14 @@ class Context:
         self._check(self._lib.mag_forces(self._h, C.byref(model), ptrs[0], kind))
         return outs[0]
 
+    def forces_exact(self, model):
+        """-dOmega/dR of the truncated-Krylov grand potential at the last
+        solve's mu, differentiated through every column's Krylov space (see
+        mag_forces_exact)."""
+        outs, ptrs, kind = self._outputs([((self.n_atoms, 3), np.float64)])
+        self._check(self._lib.mag_forces_exact(self._h, C.byref(model), ptrs[0], kind))
+        return outs[0]
+
     def icohp(self, model):
         """(B, B_sigma, B_pi) per 4x4 block of the pattern, in block-CSR order
         (Eqs. 4-8; see mag_icohp)."""

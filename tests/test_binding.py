@@ -71,6 +71,7 @@ def test_every_method_matches_the_prototypes(ctx, monkeypatch):
     ctx.green_columns([0], [0.5 + 0.1j], nu=8, kT=0.1)
     ctx.backward(1.0)
     ctx.forces(model.sk_model())
+    ctx.forces_exact(model.sk_model())
     ctx.icohp(model.sk_model())
     ctx.cohp([0.0, 1.0], 0.1)
     ctx.cocg_columns([0, 1], [0.5 + 0.1j])
