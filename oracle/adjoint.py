@@ -162,7 +162,9 @@ def exact_forces_on(geo, targets, mu, workers=None):
     targets = np.asarray(targets, dtype=np.int64)
     need = np.unique(np.concatenate(
         [_nb.cluster_of(geo.pos, geo.cell, int(I), geo.r_cluster) for I in targets]))
-    workers = workers or _pool.default_workers()
+    # these workers import torch, which opens the GPU driver in each of them
+    # on a GPU host, where the processes holding it are limited: at most 12
+    workers = min(workers or _pool.default_workers(), 12)
     if workers > 1 and need.size > 8:
         with _pool.executor(workers, initializer=_init_worker, initargs=(geo, mu)) as ex:
             res = list(ex.map(_parts_task, need.tolist(),
