@@ -163,6 +163,26 @@ int mag_sk_values(mag_ctx* ctx, const double* pos, double* H, double* S,
 int mag_sk_vjp(mag_ctx* ctx, const double* pos, const double* gH,
                const double* gS, double* grad, int mem_kind);
 
+/* Allocation-free variant of mag_sk_vjp, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  The same product on the pattern of the
+ * last mag_sk_build, grad[I] = sum_p gH[p] dH_p/dR_I + gS[p] dS_p/dR_I, with
+ * the same kernels and results bitwise equal to mag_sk_vjp's; its
+ * intermediates (the per-block parts and the block transposes) live in a
+ * fixed per-GPU array of MAG_NOALLOC_MAX_BLOCKS x 28 bytes (28 MiB) that
+ * each GPU the library runs on holds until the process ends, and the call
+ * allocates and frees nothing.  pos (n_atoms x 3), gH, gS (nnz each) and
+ * grad (n_atoms x 3) are device memory on the context's device (checked;
+ * host pointers are rejected).  The context's positions are left as they
+ * are.  Every call on one GPU uses that GPU's one array, so calls that
+ * overlap on a GPU (other threads or contexts on other streams) race.
+ * Errors: MAG_ESTATE without a build, MAG_EINVAL (NULL or non-device
+ * pointers, a pattern without transposed blocks), MAG_EUNSUPPORTED (more than
+ * MAG_NOALLOC_MAX_BLOCKS blocks in the pattern), MAG_EHIP. */
+#define MAG_NOALLOC_MAX_BLOCKS 1048576
+int mag_sk_vjp_noalloc(mag_ctx* ctx, const double* pos, const double* gH, const double* gS,
+                       double* grad);
+
 /* ---------------------------------------------------------------------- */
 /* system (H, S, clusters)                                                  */
 /* ---------------------------------------------------------------------- */

@@ -128,6 +128,7 @@ PROTOTYPES = {
     "mag_sk_get_csr": (I, [CTX, P, P, P, P, I]),
     "mag_sk_values": (I, [CTX, P, P, P, I]),
     "mag_sk_vjp": (I, [CTX, P, P, P, P, I]),
+    "mag_sk_vjp_noalloc": (I, [CTX, P, P, P, P]),
     "mag_set_system": (I, [CTX, C.POINTER(MagSystem), I]),
     "mag_update_values": (I, [CTX, P, P, I]),
     "mag_get_clusters": (I, [CTX, P, P, C.POINTER(I64), I]),

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmag.so")
-SOURCES = ["ctx.hip", "krylov.hip", "eig.hip", "mu.hip", "sk.hip", "util.hip", "md.hip", "cocg.hip", "adjoint.hip"]
+SOURCES = ["ctx.hip", "krylov.hip", "eig.hip", "mu.hip", "sk.hip", "util.hip", "md.hip", "cocg.hip", "adjoint.hip", "noalloc.hip"]
 ARCH = os.environ.get("MAG_OFFLOAD_ARCH", "gfx950")
 
 

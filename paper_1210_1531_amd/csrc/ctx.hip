@@ -807,6 +807,7 @@ int mag_create(mag_ctx** out, int device, void* hip_stream) {
     }
     ctx->own_stream = true;
   }
+  noalloc_init(device);  // the allocation-free entry point's scratch address on this device
   if (ctx->errflag.reserve(256) != hipSuccess || ctx->state.reserve(sizeof(MuState)) != hipSuccess ||
       hipMemset(ctx->errflag.p, 0, 256) != hipSuccess ||
       hipMemset(ctx->state.p, 0, sizeof(MuState)) != hipSuccess) {
@@ -977,6 +978,55 @@ int mag_sk_vjp(mag_ctx* ctx, const double* pos, const double* gH, const double* 
 // ---------------------------------------------------------------------------
 // system
 // ---------------------------------------------------------------------------
+// a device allocation on `device` holds [p, p + bytes)
+static bool device_span(const void* p, size_t bytes, int device) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (at.type != hipMemoryTypeDevice || at.device != device) return false;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (const char*)p + bytes <= (const char*)base + size;
+}
+
+int mag_sk_vjp_noalloc(mag_ctx* ctx, const double* pos, const double* gH, const double* gS,
+                       double* grad) {
+  if (!ctx) return MAG_EINVAL;
+  if (!ctx->sk_built) return fail(ctx, MAG_ESTATE, "no Slater-Koster build");
+  if (!pos || !gH || !gS || !grad) return fail(ctx, MAG_EINVAL, "NULL argument");
+  const int64_t n = ctx->sk_n, nnz = ctx->sk_nnz, nblk = ctx->sk_nblk;
+  if (nblk > NOALLOC_MAX_BLOCKS)
+    return fail(ctx, MAG_EUNSUPPORTED,
+                "the pattern has " + std::to_string(nblk) +
+                    " blocks; the allocation-free path holds at most " +
+                    std::to_string(NOALLOC_MAX_BLOCKS));
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!device_span(pos, sizeof(double) * 3 * n, ctx->device) ||
+      !device_span(gH, sizeof(double) * nnz, ctx->device) ||
+      !device_span(gS, sizeof(double) * nnz, ctx->device) ||
+      !device_span(grad, sizeof(double) * 3 * n, ctx->device))
+    return fail(ctx, MAG_EINVAL,
+                "pos, gH, gS and grad must be device memory of the documented sizes on the "
+                "context's device");
+  void* base = nullptr;
+  HIPCHK(noalloc_scratch(ctx->device, &base));
+  double* part = static_cast<double*>(base);
+  int32_t* bt = reinterpret_cast<int32_t*>(part + 3 * NOALLOC_MAX_BLOCKS);
+  HIPCHK(launch_block_transpose(ctx->sk_bptr.as<int32_t>(), ctx->sk_bcol.as<int32_t>(), n, bt,
+                                ctx->errflag.as<int32_t>(), ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_vjp_noalloc"));  // every block needs its transpose first
+  HIPCHK(launch_sk_vjp(ctx->sk_model, pos, n, nblk, ctx->sk_cell, ctx->sk_bptr.as<int32_t>(),
+                       ctx->sk_bcol.as<int32_t>(), bt, gH, gS, 1.0, part, grad, ctx->stream));
+  TRY(take_errors(ctx, "mag_sk_vjp_noalloc"));
+  return sync(ctx);
+}
+
 int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
   if (!ctx) return MAG_EINVAL;
   TRY(check_mem_kind(ctx, mem_kind));

@@ -303,6 +303,11 @@ hipError_t launch_md_drift(double* x, const double* v, int64_t n, double dt, con
 hipError_t launch_axpy(double* y, const double* x, int64_t n, double a, hipStream_t s);
 hipError_t launch_sum(const double* a, int64_t n, int squares, double* out, hipStream_t s);
 extern const double AMU_A2_FS2_EV;
+// allocation-free entry point (noalloc.hip): the fixed per-device scratch
+constexpr int64_t NOALLOC_MAX_BLOCKS = MAG_NOALLOC_MAX_BLOCKS;
+constexpr size_t NOALLOC_DOUBLES = (size_t)3 * NOALLOC_MAX_BLOCKS + NOALLOC_MAX_BLOCKS / 2;
+void noalloc_init(int device);                      // once per device, that device current
+hipError_t noalloc_scratch(int device, void** ptr);  // its device address
 hipError_t launch_sk_vjp(const SKModelDev& m, const double* pos, int64_t n, int64_t nblk,
                          const double cell[3], const int32_t* bptr, const int32_t* bcol,
                          const int32_t* btrans, const double* gH, const double* gS, double sign_gS,

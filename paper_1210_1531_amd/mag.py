@@ -175,6 +175,19 @@ class Context:
         self._check(self._lib.mag_sk_vjp(self._h, ptrs[0], ptrs[1], ptrs[2], optrs[0], okind))
         return outs[0]
 
+    def sk_vjp_noalloc(self, pos, gH, gS, out):
+        """sk_vjp without any device allocation (mag_sk_vjp_noalloc): every
+        argument is a contiguous float64 tensor on the context's device, and
+        the product is written into `out` (n_atoms x 3), which is returned."""
+        for x in (pos, gH, gS, out):
+            if not (_is_dev(x) and x.dtype == torch.float64 and x.is_contiguous()):
+                raise ValueError("sk_vjp_noalloc takes contiguous float64 device tensors")
+        self._check(self._lib.mag_sk_vjp_noalloc(self._h, C.c_void_p(pos.data_ptr()),
+                                                 C.c_void_p(gH.data_ptr()),
+                                                 C.c_void_p(gS.data_ptr()),
+                                                 C.c_void_p(out.data_ptr())))
+        return out
+
     # --------------------------------------------------------------- system
     def set_system(self, rowptr, colind, H, S, pos=None, cell=(0.0, 0.0, 0.0), r_cluster=0.0,
                    clus_ptr=None, clus_atoms=None):
