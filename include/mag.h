@@ -256,9 +256,13 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu,
  * k >= nu_eff[j] are 0) and nu_eff (M).  Any pointer may be NULL. */
 int mag_spectra(mag_ctx* ctx, double* eps, double* w, int32_t* nu_eff, int mem_kind);
 
-/* Energies of the last solve: E_band, A_free (Mermin free energy), the
- * electron count N = sum w f and the entropy sum S_ent = sum w s(f).  Any
- * pointer may be NULL. */
+/* Energies of the last solve, taken through the density matrix (the method
+ * outline after Eq. 1: energy and force through rho; Eq. 2 on the Ritz
+ * spectrum): E_band = sum_jk w_jk f_jk eps_jk (= sum_p H_p rho_p), A_free
+ * = E_band - kT S_ent (Mermin free energy), the electron count N = sum w f
+ * (= sum_p S_p rho_p, the quantity the bisection of the Eq. 3 workflow fixes)
+ * and the entropy sum S_ent = sum w s(f).  Any pointer may be NULL; host
+ * scalars.  Errors: MAG_ESTATE before a solve. */
 int mag_energy(mag_ctx* ctx, double* E_band, double* A_free, double* N_check,
                double* S_ent);
 
@@ -279,19 +283,27 @@ int mag_column_spectra(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols,
  * Runs pass 2 of the last solve's workflow.  pi may be NULL. */
 int mag_density_matrix(mag_ctx* ctx, double* rho_csr, double* pi_csr, int mem_kind);
 
-/* Full cluster columns of rho at the last solve's mu: for column cols[i] the
- * values rho_{c j} for every orbital c of its cluster in cluster order are
- * written at rho_out[offsets[i] .. offsets[i+1]), offsets[i+1] - offsets[i] =
- * 4 |C(atom of cols[i])|.  offsets (n+1, int64, host) is filled by the call;
- * pass rho_out = NULL to get the offsets only. */
+/* Full cluster columns of rho (Eq. 2 on each column's Ritz spectrum, every
+ * row of the cluster instead of the pattern; the columns of G generated one
+ * by one in the LCAO basis, the paragraph after Eq. 1) at the last solve's
+ * mu: for column cols[i] the values rho_{c j} for every orbital c of its
+ * cluster in cluster order are written at rho_out[offsets[i] ..
+ * offsets[i+1]), offsets[i+1] - offsets[i] = 4 |C(atom of cols[i])|.
+ * offsets (n+1, int64, host) is filled by the call; pass rho_out = NULL to
+ * get the offsets only.  The Krylov columns are recomputed.  Errors:
+ * MAG_ESTATE before a solve, MAG_EINVAL for column ids outside [0, M). */
 int mag_cluster_columns(mag_ctx* ctx, const int32_t* cols, int64_t n,
                         double* rho_out, int64_t* offsets, int mem_kind);
 
-/* Galerkin Green's-function columns G_{c j}(z) = sum_k Y_ck d_k / (z - eps_k)
- * (no spin factor) at nz complex energies z (re, im pairs, host), for every
- * orbital c of the cluster; output complex (re, im) at
- * G_out[2 (offsets[i] * nz + q * len_i + c)] for column i, energy q, local
- * orbital c, with offsets as in mag_cluster_columns. */
+/* Columns of the Green's function G = (zS - H)^-1 of Eq. 1 as the method
+ * approximates them: the Galerkin columns on each column's Krylov space,
+ * G_{c j}(z) = sum_k Y_ck d_k / (z - eps_k) (no spin factor), at nz complex
+ * energies z (re, im pairs, host), for every orbital c of the cluster; output
+ * complex (re, im) at G_out[2 (offsets[i] * nz + q * len_i + c)] for column
+ * i, energy q, local orbital c, with offsets as in mag_cluster_columns.  The
+ * Krylov columns are computed with `opts` (nu, breakdown) at the current
+ * system.  Errors: MAG_ESTATE without a system, MAG_EINVAL (columns, nz < 1,
+ * non-finite z). */
 int mag_green_columns(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols,
                       int64_t n, const double* z, int nz, double* G_out,
                       int64_t* offsets, int mem_kind);
@@ -300,15 +312,23 @@ int mag_green_columns(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols,
 /* derivatives                                                              */
 /* ---------------------------------------------------------------------- */
 
-/* Adjoint of A_free: dA/dH = gA * rho and dA/dS = -gA * pi on the CSR
- * pattern (nnz each; either may be NULL).  Runs pass 2 if needed. */
+/* Adjoint of A_free in the density-matrix reading of the method (energy and
+ * force through rho, after Eq. 1; Eq. 2): dA/dH = gA * rho and dA/dS =
+ * -gA * pi on the CSR pattern (nnz each, mem_kind; either may be NULL), the
+ * coefficients of H and S in E_band and in the electron count.  Runs pass 2
+ * of the last solve's workflow (Eq. 3) if needed.  Errors: MAG_ESTATE before
+ * a solve. */
 int mag_backward(mag_ctx* ctx, double gA, double* dAdH_csr, double* dAdS_csr,
                  int mem_kind);
 
-/* Forces F_I = -sum_p [rho_p dH_p/dR_I - pi_p dS_p/dR_I] (n_atoms x 3) from
- * the density matrices of the last solve and the SK derivatives of `model`
- * at the system's positions.  Requires mag_system.pos and a pattern in the
- * layout of mag_sk_build. */
+/* Forces through the density matrix (the method outline after Eq. 1: energy
+ * and force through rho): F_I = -sum_p [rho_p dH_p/dR_I - pi_p dS_p/dR_I]
+ * (n_atoms x 3, mem_kind) from the density matrices of the last solve (Eq. 2;
+ * pass 2 of Eq. 3 runs if needed) and the SK derivatives of `model` at the
+ * system's positions.  The derivative of A_free when every column's Krylov
+ * space is exact; mag_forces_exact differentiates the truncated method.
+ * Requires mag_system.pos and a pattern in the layout of mag_sk_build.
+ * Errors: MAG_ESTATE before a solve, MAG_EINVAL (model, F, no positions). */
 int mag_forces(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem_kind);
 
 /* Exact forces of the truncated-Krylov method: F_I = -dOmega/dR_I at the
