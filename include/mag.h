@@ -471,6 +471,7 @@ typedef struct {
   double t_md_step_ms;     /* last mag_md_run: average wall time of one step */
   double t_cocg_ms;        /* last mag_cocg_columns (its kernels) */
   double t_forces_exact_ms; /* last mag_forces_exact */
+  int32_t krylov_cache_blocks; /* H/S blocks of each cluster held in LDS by the largest bucket's plan */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

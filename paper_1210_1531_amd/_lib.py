@@ -109,6 +109,7 @@ class MagStats(C.Structure):
         ("t_md_step_ms", C.c_double),
         ("t_cocg_ms", C.c_double),
         ("t_forces_exact_ms", C.c_double),
+        ("krylov_cache_blocks", C.c_int32),
     ]
 
 

@@ -594,15 +594,17 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
         e2 = pool_event(ctx, 3 * timed + 2);
       }
       {
-        int used = 0, tpb = 0;
+        int used = 0, tpb = 0, cache = 0;
         for (int b = 0; b < nbk; ++b)
           if (plans[b]) {
             ++used;
+            cache = plans[b]->cache;
             for (const KrylovShapeInfo& sh : shapes)
               if (sh.id == plans[b]->shape) tpb = sh.tpb;
           }
         ctx->stats.krylov_buckets = used;
         ctx->stats.krylov_tpb = tpb;
+        ctx->stats.krylov_cache_blocks = cache;
       }
       if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
       for (int b = 0; b < nbk; ++b) {
@@ -1847,6 +1849,9 @@ int mag_forces_exact(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem
   ctx->stats.t_eig_ms = keep.t_eig_ms;
   ctx->stats.krylov_launches = keep.krylov_launches;
   ctx->stats.schedule_used = keep.schedule_used;
+  ctx->stats.krylov_buckets = keep.krylov_buckets;
+  ctx->stats.krylov_tpb = keep.krylov_tpb;
+  ctx->stats.krylov_cache_blocks = keep.krylov_cache_blocks;
   HIPCHK(launch_gather_forces(ctx->clus_ptr.as<int64_t>(), ctx->clus_atoms.as<int32_t>(), ctx->N,
                               ctx->adj_fJ.as<double>(), ctx->adj_F.as<double>(), ctx->stream));
   TRY(copy_out(ctx, F, ctx->adj_F.p, sizeof(double) * 3 * ctx->N, mem_kind));
