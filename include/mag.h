@@ -421,6 +421,8 @@ typedef struct {
   double m_rep;     /* pair repulsion exponent (> 0 when phi0 != 0) */
   double r_cluster; /* cluster radius of every column, Angstrom (<= 0: the whole cell) */
   int n_steps;      /* MD steps (>= 0) */
+  int exact_forces; /* 0: forces through rho and pi (mag_forces); 1: the exact gradient of the
+                       truncated method (mag_forces_exact, nu <= 30) */
 } mag_md_opts;
 
 /* n_steps of velocity Verlet on the potential energy E_pot = A_free + E_rep,
@@ -437,7 +439,10 @@ typedef struct {
  * the last frame's system and solve afterwards (mag_energy, mag_icohp ...).
  * Errors: as mag_sk_build, mag_set_system and mag_solve_columns, for the
  * frame at which they occur (pos and vel then hold that frame); MAG_EINVAL
- * for bad md options or NULL arrays. */
+ * for bad md options or NULL arrays.  With exact_forces the electronic force
+ * is the exact derivative of A_free of the truncated method, so E_pot + E_kin
+ * is conserved to the integrator's order; through rho it is conserved only
+ * when every Krylov space is exact. */
 int mag_md_run(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opts,
                const mag_md_opts* md, int64_t n_atoms, const double cell[3], double* pos,
                double* vel, double* F, double* thermo, int mem_kind);

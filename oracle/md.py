@@ -117,6 +117,27 @@ def krylov_forces(struct, params=None, mode="K", workers=None, phi0=None):
     return fn
 
 
+def krylov_exact_forces(struct, params=None, phi0=None, workers=None):
+    """Potential energy and forces of the truncated multiple Arnoldi method
+    with the forces as the exact derivative of its free energy (the reverse
+    mode of the Krylov construction, oracle.adjoint) instead of the
+    density-matrix reading, plus the pair repulsion: returns
+    (A_free + E_rep, F, mu, E_band)."""
+    from . import adjoint as _adj
+    p = _sk.CARBON if params is None else params
+
+    def fn(pos):
+        s = replace(struct, pos=np.asarray(pos, np.float64))
+        sysm = _solve.build_system(s, params=p)
+        r = _solve.solve(sysm, workers=workers)
+        geo = _solve.geometry(s, params=p)
+        F = _adj.exact_forces_on(geo, np.arange(s.n_atoms), r.mu, workers=workers)
+        E_rep, _, F_rep = pair_repulsion(s.pos, s.cell, phi0, p=p)
+        return r.A_free + E_rep, F + F_rep, r.mu, r.E_band
+
+    return fn
+
+
 def exact_forces(struct, params=None, phi0=None):
     """The same from the exact solution of the whole system (mode W)."""
     p = _sk.CARBON if params is None else params

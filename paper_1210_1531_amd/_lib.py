@@ -81,6 +81,7 @@ class MagMDOpts(C.Structure):
         ("m_rep", C.c_double),
         ("r_cluster", C.c_double),
         ("n_steps", C.c_int),
+        ("exact_forces", C.c_int),
     ]
 
 

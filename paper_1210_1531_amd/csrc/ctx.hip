@@ -1973,7 +1973,10 @@ static int md_frame(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opt
   TRY(mag_set_system(ctx, &sys, MAG_DEVICE));
   double mu = 0.0, E = 0.0, A = 0.0;
   TRY(mag_solve_columns(ctx, opts, &mu, &E, &A));
-  TRY(mag_forces(ctx, model, ctx->md_F.as<double>(), MAG_DEVICE));
+  if (md->exact_forces)
+    TRY(mag_forces_exact(ctx, model, ctx->md_F.as<double>(), MAG_DEVICE));
+  else
+    TRY(mag_forces(ctx, model, ctx->md_F.as<double>(), MAG_DEVICE));
   double Erep = 0.0;
   if (md->phi0 != 0.0) {
     TRY(pair_terms(ctx, md->phi0, md->m_rep));
@@ -2013,8 +2016,10 @@ int mag_md_run(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opts,
   if (!(md->dt > 0.0) || !std::isfinite(md->dt) || !(md->mass > 0.0) ||
       !std::isfinite(md->mass) || md->n_steps < 0 || !std::isfinite(md->phi0) ||
       !std::isfinite(md->r_cluster) || (md->phi0 != 0.0 && !(md->m_rep > 0.0)) ||
-      !std::isfinite(md->m_rep))
-    return fail(ctx, MAG_EINVAL, "need dt > 0, mass > 0, n_steps >= 0, finite phi0 and m_rep > 0");
+      !std::isfinite(md->m_rep) || (md->exact_forces != 0 && md->exact_forces != 1))
+    return fail(ctx, MAG_EINVAL,
+                "need dt > 0, mass > 0, n_steps >= 0, finite phi0, m_rep > 0 and exact_forces "
+                "0 or 1");
   HIPCHK(hipSetDevice(ctx->device));
   const int64_t n = n_atoms;
   ALLOC(ctx->md_x, sizeof(double) * 3 * n);

@@ -355,13 +355,14 @@ class Context:
         return e.value, outs[0], outs[1]
 
     def md_run(self, model, pos, vel, cell, dt, mass, n_steps, phi0=0.0, m_rep=4.0,
-               r_cluster=0.0, **kw):
+               r_cluster=0.0, exact_forces=False, **kw):
         """n_steps of velocity Verlet (see mag_md_run).  Returns (pos, vel, F,
         thermo) at the end; thermo[k] = (E_pot, E_kin, mu, E_band, E_rep) of
         frame k (frame 0: the start)."""
         o = make_opts(**kw)
         md = L.MagMDOpts(dt=float(dt), mass=float(mass), phi0=float(phi0), m_rep=float(m_rep),
-                         r_cluster=float(r_cluster), n_steps=int(n_steps))
+                         r_cluster=float(r_cluster), n_steps=int(n_steps),
+                         exact_forces=int(bool(exact_forces)))
         n = int(pos.shape[0])
         outs, ptrs, kind = self._outputs([((n, 3), np.float64)] * 3)
         for dst, src in zip(outs[:2], (pos, vel)):

@@ -197,3 +197,93 @@ def test_sk_build_rejects_overfull_block_rows():
     with pytest.raises(MagError) as e:
         ctx.sk_build(model.sk_model(), pos, (10.0, 10.0, 10.0))
     assert "MAG_EUNSUPPORTED" in str(e.value)
+
+
+def _md_energy_series(ctx, s, v0, dt, T, exact, torch):
+    """E_pot + E_kin - its start at every frame of a run of T fs."""
+    from paper_1210_1531_amd import model
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    _, _, _, th = ctx.md_run(model.sk_model(), dev(s.pos), dev(v0), s.cell, dt, MASS,
+                             int(round(T / dt)), phi0=PHI0, m_rep=MREP, r_cluster=s.r_cluster,
+                             nu=s.nu, kT=s.kT, n_electrons=s.n_electrons, exact_forces=exact)
+    E = th[:, 0] + th[:, 1]
+    return E - E[0]
+
+
+def test_md_with_exact_forces_matches_oracle():
+    """Frames of velocity Verlet driven by the exact gradient of the truncated
+    method (61-atom whole-cell clusters, nu = 12) against the oracle's."""
+    torch = torch_cuda()
+    from oracle import md
+    from paper_1210_1531_amd import Context, model
+    s = gs.make("tiny")
+    v0 = gs.random_velocities(s.n_atoms, _sigma(300.0), 25)
+    dt, steps = 0.25, 2
+    log(f"[md exact] {s.n_atoms} atoms, {steps} steps of {dt} fs")
+    ctx = Context()
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    pos, vel, F, th = ctx.md_run(model.sk_model(), dev(s.pos), dev(v0), s.cell, dt, MASS, steps,
+                                 phi0=PHI0, m_rep=MREP, r_cluster=s.r_cluster, nu=s.nu, kT=s.kT,
+                                 n_electrons=s.n_electrons, exact_forces=True)
+    fr = md.velocity_verlet(s.pos, v0, s.cell, md.krylov_exact_forces(s, phi0=PHI0), MASS, dt,
+                            steps)
+    dx = np.abs(_min_image(np_(pos) - fr[-1].pos, s.cell)).max()
+    dv = np.abs(np_(vel) - fr[-1].vel).max()
+    dF = np.abs(np_(F) - fr[-1].F).max()
+    log(f"[md exact] max |dx| {dx:.3e} A, |dv| {dv:.3e} A/fs, |dF| {dF:.3e} eV/A")
+    assert dF <= F_TOL and dx <= 1e-10 and dv <= 1e-11
+    for k, f in enumerate(fr):
+        assert abs(th[k, 0] - f.E_pot) / s.n_atoms <= E_TOL
+
+
+def test_md_energy_error_order_exact_against_rho_forces():
+    """With the exact gradient the energy error of velocity Verlet is second
+    order in dt (ratio 4 on halving dt, at the common times); with the forces
+    through rho it stays as dt shrinks (the part of the gradient that rho
+    misses does work along the path)."""
+    torch = torch_cuda()
+    from paper_1210_1531_amd import Context
+    s = gs.make("tiny")
+    v0 = gs.random_velocities(s.n_atoms, _sigma(300.0), 7)
+    ctx = Context()
+    rms = {}
+    for exact in (True, False):
+        a = _md_energy_series(ctx, s, v0, 0.25, 1.5, exact, torch)
+        b = _md_energy_series(ctx, s, v0, 0.125, 1.5, exact, torch)
+        rms[exact] = (np.sqrt(np.mean(a[1:] ** 2)), np.sqrt(np.mean(b[2::2] ** 2)))
+    r_exact = rms[True][0] / rms[True][1]
+    r_rho = rms[False][0] / rms[False][1]
+    log(f"[md order] rms dE exact {rms[True][0]:.2e} -> {rms[True][1]:.2e} (ratio {r_exact:.2f}), "
+        f"rho {rms[False][0]:.2e} -> {rms[False][1]:.2e} (ratio {r_rho:.2f})")
+    assert 3.5 < r_exact < 4.8
+    assert 0.8 < r_rho < 1.25
+    assert rms[False][1] > 20 * rms[True][1]
+
+
+def test_md_exact_forces_option_is_checked():
+    import ctypes as C
+    torch = torch_cuda()
+    from paper_1210_1531_amd import Context, MagError, model
+    from paper_1210_1531_amd import _lib as L
+    from paper_1210_1531_amd.mag import make_opts
+    s = gs.make("tiny")
+    ctx = Context()
+    x = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(x)
+    F = torch.zeros_like(x)
+    thermo = np.zeros((2, 5))
+    o = make_opts(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    cell = (C.c_double * 3)(*[float(c) for c in s.cell])
+    for flag, expect in ((2, L.MAG_EINVAL), (-1, L.MAG_EINVAL)):
+        md = L.MagMDOpts(dt=0.5, mass=MASS, phi0=0.0, m_rep=4.0, r_cluster=0.0, n_steps=1,
+                         exact_forces=flag)
+        rc = ctx._lib.mag_md_run(ctx._h, C.byref(model.sk_model()), C.byref(o), C.byref(md),
+                                 s.n_atoms, cell, C.c_void_p(x.data_ptr()),
+                                 C.c_void_p(v.data_ptr()), C.c_void_p(F.data_ptr()),
+                                 thermo.ctypes.data_as(C.POINTER(C.c_double)), L.MAG_DEVICE)
+        assert rc == expect
+    # nu above the exact-gradient kernels: refused at the first frame
+    with pytest.raises(MagError) as err:
+        ctx.md_run(model.sk_model(), x, v, s.cell, 0.5, MASS, 1, nu=40, kT=s.kT,
+                   n_electrons=s.n_electrons, exact_forces=True)
+    assert err.value.status == L.MAG_EUNSUPPORTED
