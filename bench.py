@@ -552,15 +552,23 @@ def main(argv=None):
         vel = torch.tensor(gen.random_velocities(s.n_atoms, model.thermal_sigma(300.0), 1),
                            dtype=torch.float64, device="cuda")
         md_kw = dict(r_cluster=s.r_cluster, **model.PAIR_REPULSION, **opts)
-        ctx.md_run(sk, pos, vel, s.cell, 0.5, model.MASS_CARBON, 1, **md_kw)
-        _, _, _, th = ctx.md_run(sk, pos, vel, s.cell, 0.5, model.MASS_CARBON, args.md_steps,
-                                 **md_kw)
-        t_md = ctx.stats()["t_md_step_ms"]
-        e_tot = th[:, 0] + th[:, 1]
-        out["md"] = {"ms_per_step": t_md, "steps": args.md_steps, "dt_fs": 0.5,
-                     "columns_per_s": M / (t_md * 1e-3),
-                     "E_tot_change_per_atom": float(e_tot[-1] - e_tot[0]) / s.n_atoms,
-                     "step": "rebuild H, S, pattern, clusters + fwd + bwd + forces + pair term"}
+        kinds = [("md", False)] + ([] if args.no_exact else [("md_exact_forces", True)])
+        for name, exact in kinds:
+            ctx.md_run(sk, pos, vel, s.cell, 0.5, model.MASS_CARBON, 1, exact_forces=exact,
+                       **md_kw)
+            _, _, _, th = ctx.md_run(sk, pos, vel, s.cell, 0.5, model.MASS_CARBON, args.md_steps,
+                                     exact_forces=exact, **md_kw)
+            t_md = ctx.stats()["t_md_step_ms"]
+            e_tot = th[:, 0] + th[:, 1]
+            out[name] = {"ms_per_step": t_md, "steps": args.md_steps, "dt_fs": 0.5,
+                         "columns_per_s": M / (t_md * 1e-3),
+                         "E_tot_change_per_atom": float(e_tot[-1] - e_tot[0]) / s.n_atoms,
+                         "E_tot_max_dev_per_atom": float(np.abs(e_tot - e_tot[0]).max())
+                         / s.n_atoms,
+                         "forces": "exact gradient of the truncated method" if exact
+                         else "through rho and pi",
+                         "step": "rebuild H, S, pattern, clusters + fwd + bwd + forces + pair "
+                                 "term"}
     if args.copy_probe:
         a = torch.full((64 * 1024 * 1024,), 1.0, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

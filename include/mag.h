@@ -231,10 +231,14 @@ typedef struct {
   double breakdown;   /* Krylov breakdown threshold, relative (<= 0: 1e-12) */
   int workflow;       /* mag_workflow */
   int schedule;       /* mag_schedule */
+  int eig_sweeps;     /* QL sweeps recorded per column (<= 0: the library's cap, 4 nu up
+                         to 128); a column that needs more is finished by the one-wave
+                         QL that applies its rotations directly (same results to rounding) */
 } mag_opts;
 
 /* Fill opts with the defaults (nu 30, kT 0.1, n_electrons 0 (must be set),
- * mu_tol 1e-12, mu_fixed NaN, breakdown 1e-12, workflow AUTO, schedule AUTO). */
+ * mu_tol 1e-12, mu_fixed NaN, breakdown 1e-12, workflow AUTO, schedule AUTO,
+ * eig_sweeps 0). */
 void mag_opts_default(mag_opts* opts);
 
 /* Pass 1 of Eq. 3 over every column, then mu, then the energies.

@@ -70,6 +70,7 @@ class MagOpts(C.Structure):
         ("breakdown", C.c_double),
         ("workflow", C.c_int),
         ("schedule", C.c_int),
+        ("eig_sweeps", C.c_int),
     ]
 
 

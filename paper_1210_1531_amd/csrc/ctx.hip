@@ -180,6 +180,7 @@ struct ColumnJob {
   std::vector<int32_t> cols_host;     // same, host copy
   int nu = 30;
   double breakdown = 1e-12;
+  int eig_sweeps = 0;      // > 0: fewer recorded QL sweeps than the buffers hold
   int schedule = MAG_SCHED_AUTO;
   int full = 0;            // write every cluster row of Q
   // eig outputs
@@ -516,7 +517,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
     ea.fb_list = ctx->k_fbl.as<int32_t>();
     ea.fb_count = ctx->k_fbc.as<int32_t>();
     ea.rec_cap = rec_cap;
-    ea.sweep_cap = sweep_cap;
+    ea.sweep_cap = job.eig_sweeps > 0 ? std::min(job.eig_sweeps, sweep_cap) : sweep_cap;
     ea.cvec = job.consumer == 4 ? ctx->adj_cvec.as<double>() : nullptr;
     ea.cdg = job.consumer == 4 ? ctx->adj_cdg.as<double>() : nullptr;
 
@@ -759,6 +760,7 @@ int ensure_density(mag_ctx* ctx) {
     job.cols_host = ctx->h_order;
     job.nu = ctx->nu;
     job.breakdown = ctx->opts.breakdown > 0 ? ctx->opts.breakdown : 1e-12;
+    job.eig_sweeps = ctx->opts.eig_sweeps;
     job.schedule = ctx->opts.schedule;
     // recomputed spectra go to scratch rows so the pass-1 data stay as they are
     ALLOC(ctx->tmp_cols, sizeof(double) * 2 * ctx->M * ctx->nu + sizeof(int32_t) * ctx->M);
@@ -844,6 +846,7 @@ void mag_opts_default(mag_opts* o) {
   o->breakdown = 1e-12;
   o->workflow = MAG_WORKFLOW_AUTO;
   o->schedule = MAG_SCHED_AUTO;
+  o->eig_sweeps = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1500,6 +1503,7 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
   job.cols_host = ctx->h_order;
   job.nu = nu;
   job.breakdown = opts->breakdown > 0 ? opts->breakdown : 1e-12;
+  job.eig_sweeps = opts->eig_sweeps;
   job.schedule = opts->schedule;
   job.eps = ctx->eps.as<double>();
   job.w = ctx->w.as<double>();
@@ -1579,6 +1583,7 @@ int mag_column_spectra(mag_ctx* ctx, const mag_opts* opts, const int32_t* cols, 
   job.cols_dev = dcols.as<int32_t>();
   job.nu = opts->nu;
   job.breakdown = opts->breakdown > 0 ? opts->breakdown : 1e-12;
+  job.eig_sweeps = opts->eig_sweeps;
   job.schedule = opts->schedule;
   job.eps = out.as<double>();
   job.w = job.eps + n * opts->nu;
@@ -1625,6 +1630,7 @@ static int full_columns(mag_ctx* ctx, const mag_opts* o, const std::vector<int32
   job.cols_host = hcols;
   job.nu = o->nu;
   job.breakdown = o->breakdown > 0 ? o->breakdown : 1e-12;
+  job.eig_sweeps = o->eig_sweeps;
   job.schedule = MAG_SCHED_GRID;
   job.full = 1;
   job.eps = spec.as<double>();
@@ -1835,6 +1841,7 @@ int mag_forces_exact(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem
   job.cols_host = ctx->h_order;
   job.nu = ctx->nu;
   job.breakdown = ctx->opts.breakdown > 0 ? ctx->opts.breakdown : 1e-12;
+  job.eig_sweeps = ctx->opts.eig_sweeps;
   job.schedule = MAG_SCHED_PERSISTENT;
   // the first pass's spectra stay as they are: this pass writes scratch rows
   ALLOC(ctx->tmp_cols, sizeof(double) * 2 * ctx->M * ctx->nu + sizeof(int32_t) * ctx->M);

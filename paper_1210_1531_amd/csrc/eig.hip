@@ -9,23 +9,29 @@
 //     C = L^-1 h L^-T, and the Householder tridiagonalization
 //     C = Q_H T Q_H^T, Q_H = P_0 P_1 ... P_{n-3}, P_k = I - beta_k v_k v_k^T
 //     (Golub & Van Loan's house vectors, v_k[k+1] = 1).  L overwrites the h
-//     block of the column's scratch, the dense reflector rows v_k the s block.
+//     block of the column's scratch (by columns, 1 / L_ii on the diagonal),
+//     the dense reflector rows v_k the s block, all zero past n.
 //  2. QL (one lane per column): the implicit QL method with Wilkinson-type
-//     shifts on T (diagonal d, subdiagonal e) gives the eigenvalues.  The
-//     plane rotations of every sweep are recorded instead of applied, so each
-//     lane carries only d and e.
+//     shifts on T (diagonal d, subdiagonal e) gives the eigenvalues, in the
+//     steps of EISPACK's imtql1/imtql2 (Martin & Wilkinson).  The plane
+//     rotations of every sweep are recorded instead of applied, each at a
+//     fixed place (sweep, plane), so each lane carries only d and e.  The
+//     lanes of a wave run their sweeps in lockstep trips, each rotation step
+//     straight-line code under a lane predicate.
 //  3. vectors (one wave per column): Z_T is rebuilt by replaying the recorded
 //     rotations on Z = I (lane i holds row i of Z; every register index is a
-//     compile-time constant), then c = L^-T Q_H Z_T column by column (lane k
-//     holds eigenvector k), so h c = eps s c and c^T s c = I.  Then
+//     compile-time constant; the rotations come through scalar loads, eight
+//     planes at a time, with the identity in planes outside the sweep), then
+//     c = L^-T Q_H Z_T column by column (lane k holds eigenvector k), so
+//     h c = eps s c and c^T s c = I.  Then
 //       d = c^T u = (Qc)^T e_l,  g = c^T s e_1 = (Qc)^T S_C e_l  (q_1 = e_l),
 //       w_k = 2 d_k g_k (spin factor 2), eigenpairs ranked ascending,
 //     and optionally P_pk = (Q_pat c)_pk d_k on the pattern rows, from which
 //     pass 2 forms rho = 2 P f and pi = 2 P (f eps) (Eq. 2 on the Ritz
 //     spectrum).
-//  A column whose rotation record would overflow its fixed slots (or whose
-//  QL did not converge in the lane kernel) is finished by a fallback kernel
-//  that runs the same QL inside one wave with the rotations applied directly.
+//  A column whose sweeps would overflow the record (or whose QL did not
+//  converge in the lane kernel) is finished by a fallback kernel that runs
+//  the same QL inside one wave with the rotations applied directly.
 #include <algorithm>
 
 #include "mag_internal.h"
@@ -36,8 +42,11 @@ namespace mag {
 constexpr int ETPB = 64;
 constexpr int QL_MAXIT = 60;  // QL iterations per eigenvalue before giving up
 
-int eig_rec_cap(int cap) { return 2 * cap * cap; }
-int eig_sweep_cap(int cap) { return std::min(4 * cap, 128); }  // two header registers per lane
+// rotation records: sweep q, plane i at q * eig_sweep_stride + i (planes padded to a
+// multiple of eight so that the replay loads whole groups of eight)
+constexpr int eig_sweep_stride(int cap) { return (cap - 1 + 7) / 8 * 8; }
+int eig_sweep_cap(int cap) { return std::min(4 * cap, 128); }
+int eig_rec_cap(int cap) { return eig_sweep_cap(cap) * eig_sweep_stride(cap); }
 
 // ---------------------------------------------------------------------------
 // 1. Cholesky, C = L^-1 h L^-T, Householder tridiagonalization.  Lane i keeps
@@ -78,7 +87,7 @@ __global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
     L[t] = in ? s[hi * NM + lo] : 0.0;
     X[t] = in ? h[hi * NM + lo] : 0.0;
   }
-  if (row) tr[3 * NM + lane] = L[0];  // s e_1
+  if (lane < NM) tr[3 * NM + lane] = L[0];  // s e_1 (zero past n)
 
   // ---- Cholesky s = L L^T, column c after column c: row c comes from lane c
   bool notpd = false;
@@ -141,11 +150,12 @@ __global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
 #pragma unroll
     for (int t = 0; t < NM; ++t) X[t] = 0.5 * (X[t] + sm[lane * LD + t]);
   }
-  // L (zero above the diagonal) over h
-  if (row) {
+  // L by columns over h (column t at t * NM), 1 / L_tt on the diagonal, zero
+  // above it and past n
+  if (lane < NM) {
 #pragma unroll
     for (int t = 0; t < NM; ++t)
-      if (t < n) h[lane * NM + t] = (t <= lane) ? L[t] : 0.0;
+      h[t * NM + lane] = (row && t < n && t <= lane) ? ((t == lane) ? linv : L[t]) : 0.0;
   }
 
   // ---- Householder: step j reflects rows and columns j+1..n-1 so that column
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
         tr[NM + j] = sub;
         tr[2 * NM + j] = beta;
       }
-      if (row) s[j * NM + lane] = vi;  // dense reflector row j
+      if (lane < NM) s[j * NM + lane] = vi;  // dense reflector row j (zero past n)
       if (beta != 0.0) {
         // p = beta C v (lane k: its column against v), w = p - (beta p^T v / 2) v
         double vb[NM];
@@ -221,11 +231,16 @@ __global__ __launch_bounds__(ETPB) void tri_kernel(EigArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 2. QL on the tridiagonal, one lane per column, rotations recorded per sweep
+// 2. QL on the tridiagonal, one lane per column, rotations recorded per sweep.
+// The lanes of a wave sit at different eigenvalues l and sweep lengths, so
+// the loop is flattened into trips: in each trip a lane either deflates
+// (ms == l: l advances) or runs one sweep.  Every rotation slot of a sweep is
+// straight-line code under a lane predicate (values selected, not branched
+// over), and a slot that no lane of the wave needs is skipped as a whole.
 template <int NM>
 __global__ __launch_bounds__(ETPB) void ql_kernel(EigArgs a) {
   const int64_t slot = (int64_t)blockIdx.x * ETPB + threadIdx.x;
-  if (slot >= a.ncols) return;  // no barriers below
+  if (slot >= a.ncols) return;  // no barriers or cross-lane reads of dead lanes below
   const int n = a.nu_eff_in[slot];
   if (n <= 0 || n > NM) {
     a.qlst[slot] = 0;
@@ -234,86 +249,96 @@ __global__ __launch_bounds__(ETPB) void ql_kernel(EigArgs a) {
   const double* tr = a.trid + slot * (int64_t)(4 * NM);
   double d[NM], e[NM];
 #pragma unroll
-  for (int t = 0; t < NM; ++t) {
-    d[t] = (t < n) ? tr[t] : 0.0;
-    e[t] = (t < n) ? tr[NM + t] : 0.0;
+  for (int t = 0; t < NM; ++t) {  // whole rows (in bounds), entries past n replaced
+    const double dt = tr[t], et = tr[NM + t];
+    d[t] = (t < n) ? dt : 0.0;
+    e[t] = (t < n) ? et : 0.0;
   }
   double2* rec = reinterpret_cast<double2*>(a.rot) + slot * (int64_t)a.rec_cap;
   int32_t* sw = a.sweep + slot * (int64_t)a.sweep_cap;
-  int nrec = 0, nsw = 0, status = 0;
-  for (int l = 0; l < n && status == 0; ++l) {
-    for (int iter = 0;; ++iter) {
-      int ms = n - 1;
+  constexpr int SWS = eig_sweep_stride(NM);
+  int nsw = 0, status = 0, l = 0, iter = 0;
+  for (;;) {
+    const bool live = status == 0 && l < n;
+    if (__builtin_amdgcn_ballot_w64(live) == 0) break;
+    // ms: the first negligible subdiagonal at or after l.  e is zero from
+    // n - 1 on, so ms = n - 1 when none is negligible before it
+    int ms = NM - 1;
+    double dm = d[NM - 1];
 #pragma unroll
-      for (int t = NM - 2; t >= 0; --t) {
-        if (t >= l && t < n - 1) {
-          if (fabs(e[t]) <= 0x1p-52 * (fabs(d[t]) + fabs(d[t + 1]))) ms = t;
-        }
-      }
-      if (ms == l) break;
-      if (iter >= QL_MAXIT) {
-        status = -2;
-        break;
-      }
-      if (nsw >= a.sweep_cap || nrec + (ms - l) > a.rec_cap) {
-        status = -1;
-        break;
-      }
-      double dl = 0.0, dl1 = 0.0, el = 0.0, dm = 0.0;
+    for (int t = NM - 2; t >= 0; --t) {
+      const bool neg = t >= l && fabs(e[t]) <= 0x1p-52 * (fabs(d[t]) + fabs(d[t + 1]));
+      ms = neg ? t : ms;
+      dm = neg ? d[t] : dm;
+    }
+    bool sweep = live && ms != l;
+    if (live && ms == l) {
+      ++l;
+      iter = 0;
+    }
+    if (sweep && iter >= QL_MAXIT) {
+      status = -2;
+      sweep = false;
+    }
+    if (sweep && nsw >= a.sweep_cap) {
+      status = -1;
+      sweep = false;
+    }
+    if (__builtin_amdgcn_ballot_w64(sweep) == 0) continue;
+    // Wilkinson-type shift from the leading 2 x 2 block at l
+    double dl = 0.0, dl1 = 0.0, el = 1.0;
 #pragma unroll
-      for (int t = 0; t < NM; ++t) {
-        if (t == l) {
-          dl = d[t];
-          el = e[t];
-        }
-        if (t == l + 1) dl1 = d[t];
-        if (t == ms) dm = d[t];
-      }
-      double g = (dl1 - dl) / (2.0 * el);
-      double r = sqrt(fma(g, g, 1.0));
-      g = dm - dl + el / (g + copysign(r, g));
-      double sn = 1.0, cs = 1.0, p = 0.0;
-      bool under = false;
-      int cnt = 0;
+    for (int t = 0; t < NM; ++t) {
+      dl = (t == l) ? d[t] : dl;
+      el = (sweep && t == l) ? e[t] : el;
+      dl1 = (t == l + 1) ? d[t] : dl1;
+    }
+    double g = (dl1 - dl) / (2.0 * el);
+    double r = sqrt(fma(g, g, 1.0));
+    g = dm - dl + el / (g + copysign(r, g));
+    double sn = 1.0, cs = 1.0, p = 0.0;
+    bool under = false;
+    int cnt = 0;
+    // slot i rotates the plane (i, i+1); the sweep runs i = ms-1 down to l.
+    // Its last step (i = l, unless it ended early by underflow) also takes
+    // d[l] -= p, e[l] = g, and its first step leaves e[ms] = 0
 #pragma unroll
-      for (int i = NM - 2; i >= 0; --i) {
-        if (i >= ms) continue;
-        if (i < l || under) break;
-        const double f = sn * e[i], b = cs * e[i];
-        // r = |(f, g)|; r == 0 only by underflow, and then the identity rotation
-        // (sn, cs) = (0, 1) gives d[i+1] -= p, and the sweep ends
-        const double q = fma(f, f, g * g);
-        const bool bad = !(q > 0.0);
-        const double rinv = bad ? 0.0 : rsqrt(q);
-        r = q * rinv;
-        e[i + 1] = r;
-        sn = f * rinv;
-        cs = bad ? 1.0 : g * rinv;
-        g = d[i + 1] - p;
-        r = fma(d[i] - g, sn, 2.0 * cs * b);
-        p = sn * r;
-        d[i + 1] = g + p;
-        g = fma(cs, r, -b);
-        rec[nrec + cnt] = make_double2(sn, cs);
-        ++cnt;
-        under = bad;
-      }
+    for (int i = NM - 2; i >= 0; --i) {
+      const bool act = sweep && i < ms && i >= l && !under;
+      if (__builtin_amdgcn_ballot_w64(act) == 0) continue;
+      const double f = sn * e[i], b = cs * e[i];
+      // r = |(f, g)|; r == 0 only by underflow, and then the identity rotation
+      // (sn, cs) = (0, 1) gives d[i+1] -= p, and the sweep ends
+      const double q = fma(f, f, g * g);
+      const bool bad = !(q > 0.0);
+      const double rinv = bad ? 0.0 : rsqrt(bad ? 1.0 : q);
+      const double sn1 = f * rinv;
+      const double cs1 = bad ? 1.0 : g * rinv;
+      const double g1 = d[i + 1] - p;
+      const double r1 = fma(d[i] - g1, sn1, 2.0 * cs1 * b);
+      const double p1 = sn1 * r1;
+      const double g2 = fma(cs1, r1, -b);
+      if (act) rec[nsw * SWS + i] = make_double2(sn1, cs1);
+      e[i + 1] = act ? ((i + 1 == ms) ? 0.0 : q * rinv) : e[i + 1];
+      d[i + 1] = act ? g1 + p1 : d[i + 1];
+      const bool fin = act && i == l && !bad;
+      d[i] = fin ? d[i] - p1 : d[i];
+      e[i] = fin ? g2 : e[i];
+      sn = act ? sn1 : sn;
+      cs = act ? cs1 : cs;
+      p = act ? p1 : p;
+      g = act ? g2 : g;
+      under = under || (act && bad);
+      cnt += act ? 1 : 0;
+    }
+    if (sweep) {
       sw[nsw++] = (ms << 8) | cnt;
-      nrec += cnt;
-#pragma unroll
-      for (int t = 0; t < NM; ++t) {
-        if (!under && t == l) {
-          d[t] -= p;
-          e[t] = g;
-        }
-        if (t == ms) e[t] = 0.0;
-      }
+      ++iter;
     }
   }
   double* ev = a.evu + slot * (int64_t)NM;
 #pragma unroll
-  for (int t = 0; t < NM; ++t)
-    if (t < n) ev[t] = d[t];
+  for (int t = 0; t < NM; ++t) ev[t] = d[t];  // zero past n
   a.qlst[slot] = (status == 0) ? nsw : status;
   if (status != 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)slot;
 }
@@ -399,7 +424,15 @@ __device__ __forceinline__ bool ql_wave(const double* tr, int n, double* z, doub
 }
 
 // ---------------------------------------------------------------------------
-// 3. eigenvectors, spectral weights and pattern rows
+// 3. eigenvectors, spectral weights and pattern rows.  One wave per column,
+// lane k carries eigenvector k.  Everything this kernel reads of the column
+// (rotation record, reflectors, L, the rows of Q) was written by earlier
+// kernels and is the same for every lane, so it is read through the constant
+// address space: scalar loads into SGPRs that feed the FMAs directly, no LDS
+// staging and no cross-lane broadcasts.
+typedef const __attribute__((address_space(4))) double kdouble;
+typedef const __attribute__((address_space(4))) int32_t kint;
+
 template <int NM, bool FB>
 __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, double* sm) {
   constexpr int LD = NM + 1;
@@ -416,76 +449,57 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
     if (lane == 0) a.nu_eff_out[oi] = 0;
     return;
   }
-  double* T = sm;              // NM x LD: rows of Z, then the reflectors
-  double* Lm = T + NM * LD;    // NM x LD: L, zero padded
-  double* uu = Lm + NM * LD;   // row l of Q
-  double* s0 = uu + NM;        // s e_1
-  double* li = s0 + NM;        // 1 / L_ii
-  double* ev = li + NM;        // eigenvalues (unsorted)
-  const double* hL = a.hs + slot * (int64_t)(2 * NM * NM);
-  const double* hV = hL + NM * NM;
-  const double* tr = a.trid + slot * (int64_t)(4 * NM);
+  double* T = sm;            // NM x LD: rows of Z, read back as columns
+  double* ev = T + NM * LD;  // eigenvalues (unsorted)
+  // L by columns (1 / L_ii on the diagonal), the reflector rows, the
+  // tridiagonal's scratch: all zero past n
+  kdouble* hL = (kdouble*)(a.hs + slot * (int64_t)(2 * NM * NM));
+  kdouble* hV = hL + NM * NM;
+  kdouble* tr = (kdouble*)(a.trid + slot * (int64_t)(4 * NM));
 
-  for (int idx = lane; idx < NM * NM; idx += ETPB) {
-    const int i = idx / NM, k = idx - (idx / NM) * NM;
-    Lm[i * LD + k] = (i < n && k < n) ? hL[i * NM + k] : 0.0;
-  }
-  if (lane < NM) {
-    uu[lane] = (lane < n) ? a.urow[slot * (int64_t)NM + lane] : 0.0;
-    s0[lane] = (lane < n) ? tr[3 * NM + lane] : 0.0;
-    li[lane] = (lane < n) ? 1.0 / hL[lane * NM + lane] : 0.0;
-  }
-
-  // ---- Z_T: rows of the identity, rotated
+  // ---- Z_T: rows of the identity, rotated (lane i holds row i)
   double z[NM];
 #pragma unroll
   for (int t = 0; t < NM; ++t) z[t] = (t == lane) ? 1.0 : 0.0;
   if (!FB) {
     const int nsw = a.qlst[slot];
-    const double2* rec = reinterpret_cast<const double2*>(a.rot) + slot * (int64_t)a.rec_cap;
-    const int32_t* sw = a.sweep + slot * (int64_t)a.sweep_cap;
-    // every sweep header in registers (lane q holds sweeps q and q + 64), and
-    // the next sweep's rotations loaded while the current one is applied
-    const int h0 = lane < nsw ? sw[lane] : 0;
-    const int h1 = lane + 64 < nsw ? sw[lane + 64] : 0;
-    auto header = [&](int q) {
-      return q < 64 ? __builtin_amdgcn_readlane(h0, q) : __builtin_amdgcn_readlane(h1, q - 64);
-    };
-    // lane t holds the rotation of the plane (t, t+1); sweep (ms, cnt) ran t = ms-1 down to ms-cnt
-    auto fetch = [&](int hdr, int ptr) {
-      const int ms = hdr >> 8, lo = ms - (hdr & 255);
-      double2 r = make_double2(0.0, 1.0);
-      if (lane < ms && lane >= lo) r = rec[ptr + (ms - 1 - lane)];
-      return r;
-    };
-    int hdr = nsw > 0 ? header(0) : 0;
-    int ptr = 0;
-    double2 next = fetch(hdr, 0);
+    constexpr int SWS = eig_sweep_stride(NM);
+    kdouble* rec = (kdouble*)(a.rot + slot * (int64_t)(2 * a.rec_cap));  // (sn, cs) pairs
+    kint* sw = (kint*)(a.sweep + slot * (int64_t)a.sweep_cap);
+    // sweep (ms, cnt) rotated the planes i = ms-1 down to ms-cnt, in that order;
+    // its record is read eight planes at a time (two 64-byte scalar loads)
+    int hdr_next = nsw > 0 ? sw[0] : 0;
     for (int q = 0; q < nsw; ++q) {
-      const int ms = hdr >> 8, cnt = hdr & 255;
-      const int lo = ms - cnt;
-      const double2 rt = next;
-      const int ptr_n = ptr + cnt;
-      const int hdr_n = (q + 1 < nsw) ? header(q + 1) : 0;
-      if (q + 1 < nsw) next = fetch(hdr_n, ptr_n);
+      const int hdr = hdr_next;
+      if (q + 1 < nsw) hdr_next = sw[q + 1];  // in flight with the first group's loads
+      const int ms = hdr >> 8;
+      const int lo = ms - (hdr & 255);
+      kdouble* rq = rec + 2 * (int64_t)q * SWS;
 #pragma unroll
-      for (int i = NM - 2; i >= 0; --i) {
-        if (i < ms && i >= lo) {
-          const double sn = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(rt.x), i),
-                                             __builtin_amdgcn_readlane(__double2loint(rt.x), i));
-          const double cs = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(rt.y), i),
-                                             __builtin_amdgcn_readlane(__double2loint(rt.y), i));
-          const double zf = z[i + 1];
-          z[i + 1] = fma(sn, z[i], cs * zf);
-          z[i] = fma(cs, z[i], -sn * zf);
+      for (int c = SWS / 8 - 1; c >= 0; --c) {
+        if (8 * c < ms && 8 * c + 8 > lo) {
+          double rr[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) rr[u] = rq[16 * c + u];
+#pragma unroll
+          for (int u = 7; u >= 0; --u) {
+            const int i = 8 * c + u;
+            if (i > NM - 2) continue;
+            // planes outside the sweep take the identity rotation (a scalar
+            // select): no per-lane predication
+            const bool on = i < ms && i >= lo;
+            const double sn = on ? rr[2 * u] : 0.0, cs = on ? rr[2 * u + 1] : 1.0;
+            const double zf = z[i + 1];
+            z[i + 1] = fma(sn, z[i], cs * zf);
+            z[i] = fma(cs, z[i], -sn * zf);
+          }
         }
       }
-      hdr = hdr_n;
-      ptr = ptr_n;
     }
     if (lane < n) ev[lane] = a.evu[slot * (int64_t)NM + lane];
   } else {
-    if (!ql_wave<NM>(tr, n, z, ev, lane) && lane == 0) atomicOr(a.err, (int)KERR_NOCONV);
+    if (!ql_wave<NM>(a.trid + slot * (int64_t)(4 * NM), n, z, ev, lane) && lane == 0)
+      atomicOr(a.err, (int)KERR_NOCONV);
   }
   if (lane < NM) {
 #pragma unroll
@@ -503,20 +517,14 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
       rank += (f < ek || (f == ek && q2 < lane)) ? 1 : 0;
     }
   }
-  // ---- column `lane` of Z_T
+  // ---- column `lane` of Z_T (zero past n for lanes below n)
   double y[NM];
 #pragma unroll
   for (int t = 0; t < NM; ++t) y[t] = (lane < NM) ? T[t * LD + lane] : 0.0;
-  __syncthreads();
-  for (int idx = lane; idx < NM * NM; idx += ETPB) {
-    const int k = idx / NM, i = idx - (idx / NM) * NM;
-    T[k * LD + i] = (k + 2 < n && i < n) ? hV[k * NM + i] : 0.0;
-  }
-  __syncthreads();
   // ---- y = P_0 P_1 ... P_{n-3} y
   for (int k = n - 3; k >= 0; --k) {
     const double beta = tr[2 * NM + k];
-    const double* vk = T + k * LD;
+    kdouble* vk = hV + k * NM;
     double r0 = 0.0, r1 = 0.0;
 #pragma unroll
     for (int t = 0; t < NM; t += 2) {
@@ -527,21 +535,22 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
 #pragma unroll
     for (int t = 0; t < NM; ++t) y[t] = fma(-r, vk[t], y[t]);
   }
-  // ---- c = L^-T y (back substitution from the last row)
+  // ---- c = L^-T y (back substitution from the last row; column i of L)
 #pragma unroll
   for (int i = NM - 1; i >= 0; --i) {
+    kdouble* Li = hL + i * NM;
     double x = y[i];
 #pragma unroll
-    for (int p = i + 1; p < NM; ++p) x = fma(-Lm[p * LD + i], y[p], x);
-    y[i] = x * li[i];
-    __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight to one row
+    for (int p = i + 1; p < NM; ++p) x = fma(-Li[p], y[p], x);
+    y[i] = x * Li[i];
   }
   // ---- d = c^T u, g = c^T s e_1, w = 2 d g
+  kdouble* uu = (kdouble*)(a.urow + slot * (int64_t)NM);
   double dk = 0.0, gk = 0.0;
 #pragma unroll
   for (int t = 0; t < NM; ++t) {
     dk = fma(uu[t], y[t], dk);
-    gk = fma(s0[t], y[t], gk);
+    gk = fma(tr[3 * NM + t], y[t], gk);
   }
   const double wk = G_SPIN * dk * gk;
   if (a.cvec && lane < NM) {
@@ -567,26 +576,18 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
   if (a.P) {
     const int np = a.npat[slot];
     const int64_t base = a.pmode ? a.rowptr[j] : slot * (int64_t)a.pat_stride;
-    const double* qp = a.qpat + slot * (int64_t)a.pat_stride * NM;
-    // the pattern rows of Q are staged in LDS (over Z and L, free now) in
-    // chunks, with one coalesced copy per chunk, and read back as broadcasts
-    constexpr int PCH = (2 * NM * LD) / NM;
-    double* qs = T;
-    for (int p0 = 0; p0 < np; p0 += PCH) {
-      const int pc = min(PCH, np - p0);
-      __syncthreads();
-      for (int idx = lane; idx < pc * NM; idx += ETPB) qs[idx] = qp[(int64_t)p0 * NM + idx];
-      __syncthreads();
-      for (int p = 0; p < pc; ++p) {
-        const double* qrow = qs + p * NM;
-        double y0 = 0.0, y1 = 0.0;
+    kdouble* qp = (kdouble*)(a.qpat + slot * (int64_t)a.pat_stride * NM);
+    double* Prow = a.P + base * nuo + rank;
+#pragma unroll 2
+    for (int p = 0; p < np; ++p) {
+      kdouble* qrow = qp + p * NM;
+      double y0 = 0.0, y1 = 0.0;
 #pragma unroll
-        for (int t = 0; t < NM; t += 2) {
-          y0 = fma(qrow[t], y[t], y0);
-          if (t + 1 < NM) y1 = fma(qrow[t + 1], y[t + 1], y1);
-        }
-        if (lane < nuo) a.P[(base + p0 + p) * nuo + rank] = (lane < n) ? (y0 + y1) * dk : 0.0;
+      for (int t = 0; t < NM; t += 2) {
+        y0 = fma(qrow[t], y[t], y0);
+        if (t + 1 < NM) y1 = fma(qrow[t + 1], y[t + 1], y1);
       }
+      if (lane < nuo) Prow[(int64_t)p * nuo] = (lane < n) ? (y0 + y1) * dk : 0.0;
     }
   }
 }
@@ -615,7 +616,7 @@ template <int NM>
 static hipError_t launch_eig_nm(const EigArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)a.ncols;
   const size_t lds1 = (size_t)NM * (NM + 1) * sizeof(double);
-  const size_t lds3 = (size_t)2 * NM * (NM + 1) * sizeof(double) + 4 * NM * sizeof(double);
+  const size_t lds3 = (size_t)NM * (NM + 1) * sizeof(double) + NM * sizeof(double);
   hipLaunchKernelGGL(tri_kernel<NM>, dim3(nb), dim3(ETPB), lds1, s, a);
   hipError_t e = launch_fill_i32(a.fb_count, 1, 0, s);
   if (e != hipSuccess) return e;

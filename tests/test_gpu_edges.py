@@ -192,3 +192,37 @@ def test_full_cluster_columns_of_every_column():
         worst = max(worst, float(np.abs(R[off[i]:off[i + 1]] - ref).max()))
     log(f"[cluster columns] {cols.size} columns, {int(off[-1])} values, max |d rho| {worst:.2e}")
     assert worst <= RHO_TOL
+
+
+@pytest.mark.parametrize("sweeps", [1, 24])
+def test_one_wave_ql_for_columns_past_the_sweep_record(sweeps):
+    # eig_sweeps caps the QL sweeps recorded per column: with 1 every column
+    # of the 487-atom vacancy cell (nu = 30) is finished by the one-wave QL
+    # that applies its rotations directly, with 24 a part of them.  Spectra,
+    # weights and rho agree with the recorded path to rounding, and with the
+    # oracle at the parity bars
+    import gen
+    from oracle import solve
+    s = gen.make("mini_vac")
+    ctx = gpu_context(s)
+    kw = dict(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    mu0, E0, _ = ctx.solve(**kw)
+    eps0, w0, _ = (np_(x) for x in ctx.spectra())
+    rho0, _ = (np_(x) for x in ctx.density_matrix())
+    mu1, E1, _ = ctx.solve(eig_sweeps=sweeps, **kw)
+    eps1, w1, nu1 = (np_(x) for x in ctx.spectra())
+    rho1, _ = (np_(x) for x in ctx.density_matrix())
+    log(f"[one-wave QL, {sweeps} sweeps recorded] |d eps| {np.abs(eps1 - eps0).max():.1e}, "
+        f"|d w| {np.abs(w1 - w0).max():.1e}, |d rho| {np.abs(rho1 - rho0).max():.1e}, "
+        f"|d mu| {abs(mu1 - mu0):.1e}")
+    assert np.abs(eps1 - eps0).max() <= 1e-11
+    assert np.abs(w1 - w0).max() <= 1e-12
+    assert np.abs(rho1 - rho0).max() <= 1e-12
+    assert abs(E1 - E0) / s.n_atoms <= 1e-12
+    sysm = solve.build_system(s)
+    ref = solve.solve(sysm)
+    np.testing.assert_array_equal(nu1, ref.cd["nu_eff"])
+    np.testing.assert_allclose(eps1, ref.cd["eps"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(w1, ref.cd["w"], rtol=0, atol=1e-10)
+    rho_o, _ = solve.density_on_pattern(sysm, ref.cd, mu1)
+    assert np.abs(rho1 - rho_o).max() <= RHO_TOL
