@@ -184,8 +184,9 @@ def krylov_roofline(ctx, s, st, t_launch_ms, launches_per_pass=1):
         "kernel": "krylov_kernel",
         "launch_ms": t_launch_ms,
         "bytes_per_launch": per_launch,
-        "model": "streamed-cluster bytes (SURVEY 8(d)); this working set is served from "
-                 "LDS, L2 and MALL, not HBM",
+        "model": "streamed-cluster bytes: every Krylov step reads the cluster's H, S values "
+                 "and indices once, shared by the atom's four columns; this working set is "
+                 "served from LDS, L2 and MALL, not HBM",
         "vmem": {"issued_bytes_per_launch": vmem, "achieved_GBs": vmem_gbs,
                  "ceiling_GBs": VMEM_PEAK_GBS, "frac": vmem_gbs / VMEM_PEAK_GBS,
                  "cache_blocks": int(st["krylov_cache_blocks"])},
