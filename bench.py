@@ -193,6 +193,21 @@ def krylov_roofline(ctx, s, st, t_launch_ms, launches_per_pass=1):
     }
 
 
+def launch_plans(st):
+    """The launch plan chosen for each cluster-size bucket of the last pass."""
+    out = []
+    for b, tpb in enumerate(st["plan_threads"]):
+        if tpb <= 0:
+            continue
+        out.append({"bucket": b, "threads": tpb, "rows_per_thread": st["plan_rows"][b],
+                    "workgroups_per_cu": st["plan_per_cu"][b],
+                    "cached_blocks": st["plan_cache"][b],
+                    "candidates": st["plan_candidates"][b],
+                    "columns": int(st["plan_columns"][b]),
+                    "tuned_us_per_column": st["plan_us_per_col"][b]})
+    return out
+
+
 def grand_potential_columns(eps, w, nu_eff, mu, kT):
     """Per-column Omega_j = sum_k w_jk omega(eps_jk), omega(e) = -kT ln(1 +
     exp(-(e - mu)/kT)), from the GPU's Ritz data."""
@@ -277,6 +292,7 @@ def extra_workload(key, nu, Context, model, torch, steps, plain_sample):
         "workflow_used": {0: "recompute", 1: "store"}[st["workflow_used"]],
         "krylov_buckets": st["krylov_buckets"], "krylov_threads": st["krylov_tpb"],
         "autotune_ms": st_tune["autotune_ms"] - st0["autotune_ms"],
+        "krylov_plans": launch_plans(st),
         "stage_ms": {"krylov": st["t_krylov_ms"], "eig": st["t_eig_ms"],
                      "mu_energy": st["t_mu_ms"], "pass2": st["t_pass2_ms"],
                      "forces": st["t_forces_ms"]},
@@ -461,6 +477,7 @@ def main(argv=None):
             "autotune_ms": st["autotune_ms"],
             "step": "fwd (pass 1 + mu + energy) + bwd (pass 2 rho/pi + forces through rho)",
         },
+        "krylov_plans": launch_plans(st),
         "fwd_columns_per_s": M / (ms_fwd * 1e-3),
         "fwdbwd_recompute_columns_per_s": rec,
         "fwdbwd_graph_columns_per_s": graph,

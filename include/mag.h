@@ -47,6 +47,7 @@ extern "C" {
 #define MAG_NU_MAX 48       /* largest Krylov dimension */
 #define MAG_CLUSTER_MAX 192 /* largest cluster, atoms (768 orbitals) */
 #define MAG_BLOCKS_MAX 32   /* largest block row (atoms within r_cut, self included) */
+#define MAG_STATS_BUCKETS 8 /* launch plans reported per pass (cluster-size buckets) */
 
 typedef struct mag_ctx mag_ctx;
 
@@ -481,6 +482,16 @@ typedef struct {
   double t_cocg_ms;        /* last mag_cocg_columns (its kernels) */
   double t_forces_exact_ms; /* last mag_forces_exact */
   int32_t krylov_cache_blocks; /* H/S blocks of each cluster held in LDS by the largest bucket's plan */
+  /* the launch plan of each cluster-size bucket of the last pass 1 (bucket b
+     holds the clusters between the row capacities of the shapes b-1 and b;
+     entries of unused buckets are 0) */
+  int32_t plan_threads[MAG_STATS_BUCKETS];    /* threads per workgroup */
+  int32_t plan_rows[MAG_STATS_BUCKETS];       /* cluster rows per thread */
+  int32_t plan_per_cu[MAG_STATS_BUCKETS];     /* persistent workgroups per CU */
+  int32_t plan_cache[MAG_STATS_BUCKETS];      /* cluster blocks cached in LDS */
+  int32_t plan_candidates[MAG_STATS_BUCKETS]; /* plans timed for the bucket (0: not tuned) */
+  int64_t plan_columns[MAG_STATS_BUCKETS];    /* columns of the bucket */
+  double plan_us_per_col[MAG_STATS_BUCKETS];  /* the chosen plan's timed us per column */
 } mag_stats;
 
 int mag_get_stats(mag_ctx* ctx, mag_stats* out);

@@ -24,6 +24,7 @@ STATUS_NAMES = {
 
 MAG_HOST = 0
 MAG_DEVICE = 1
+MAG_STATS_BUCKETS = 8
 MAG_WORKFLOW_RECOMPUTE = 0
 MAG_WORKFLOW_STORE = 1
 MAG_WORKFLOW_AUTO = 2
@@ -112,6 +113,13 @@ class MagStats(C.Structure):
         ("t_cocg_ms", C.c_double),
         ("t_forces_exact_ms", C.c_double),
         ("krylov_cache_blocks", C.c_int32),
+        ("plan_threads", C.c_int32 * MAG_STATS_BUCKETS),
+        ("plan_rows", C.c_int32 * MAG_STATS_BUCKETS),
+        ("plan_per_cu", C.c_int32 * MAG_STATS_BUCKETS),
+        ("plan_cache", C.c_int32 * MAG_STATS_BUCKETS),
+        ("plan_candidates", C.c_int32 * MAG_STATS_BUCKETS),
+        ("plan_columns", C.c_int64 * MAG_STATS_BUCKETS),
+        ("plan_us_per_col", C.c_double * MAG_STATS_BUCKETS),
     ]
 
 

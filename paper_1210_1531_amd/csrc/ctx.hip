@@ -373,10 +373,12 @@ int krylov_tune(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shapes, int b,
   int32_t* dc = ctx->k_queue.as<int32_t>() + KRYLOV_QUEUES * (int64_t)shapes.size();
 
   std::vector<KrylovPlan> cand;
-  for (int s2 = b; s2 < (int)shapes.size(); ++s2) {
+  for (int s2 = 0; s2 < (int)shapes.size(); ++s2) {
+    if (shapes[s2].rows() < shapes[b].rows()) continue;  // too small for the bucket
     const int occ = std::max(1, krylov_occupancy(shapes[s2].id, 0));
     for (int pc = 1; pc <= occ; ++pc) cand.push_back(make_plan(shapes[s2].id, pc, ctx->device));
   }
+  plan.candidates = (int)cand.size();
   if (cand.size() < 2) return MAG_OK;  // nothing to choose
   hipEvent_t t0 = nullptr, t1 = nullptr;
   HIPCHK(hipEventCreate(&t0));
@@ -410,12 +412,39 @@ int krylov_tune(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shapes, int b,
       plan = c;
       plan.tuned = true;
       plan.us_per_col = us;
+      plan.candidates = (int)cand.size();
     }
   }
   ctx->stats.autotune_ms += tt.stop_ms();
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   return MAG_OK;
+}
+
+// the plans of the pass's buckets, for mag_get_stats
+static void record_plans(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shapes,
+                         const std::vector<const KrylovPlan*>& plans,
+                         const std::vector<int64_t>& boff) {
+  mag_stats& st = ctx->stats;
+  for (int b = 0; b < MAG_STATS_BUCKETS; ++b) {
+    st.plan_threads[b] = st.plan_rows[b] = st.plan_per_cu[b] = 0;
+    st.plan_cache[b] = st.plan_candidates[b] = 0;
+    st.plan_columns[b] = 0;
+    st.plan_us_per_col[b] = 0.0;
+  }
+  for (int b = 0; b < (int)plans.size() && b < MAG_STATS_BUCKETS; ++b) {
+    if (!plans[b]) continue;
+    for (const KrylovShapeInfo& sh : shapes)
+      if (sh.id == plans[b]->shape) {
+        st.plan_threads[b] = sh.tpb;
+        st.plan_rows[b] = sh.r;
+      }
+    st.plan_per_cu[b] = plans[b]->per_cu;
+    st.plan_cache[b] = plans[b]->cache;
+    st.plan_candidates[b] = plans[b]->candidates;
+    st.plan_columns[b] = boff[b + 1] - boff[b];
+    st.plan_us_per_col[b] = plans[b]->us_per_col;
+  }
 }
 
 int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
@@ -606,6 +635,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
         ctx->stats.krylov_buckets = used;
         ctx->stats.krylov_tpb = tpb;
         ctx->stats.krylov_cache_blocks = cache;
+        record_plans(ctx, shapes, plans, boff);
       }
       if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
       for (int b = 0; b < nbk; ++b) {

@@ -630,8 +630,10 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
 // (256 and 512 threads) and a one-row 768-thread shape whose basis does not
 // fit the 168 registers and partly spills: on the void cell's large clusters
 // it still runs 1.3-1.4 times faster than the two-row shape that holds them.
-// The library picks a shape per bucket of cluster sizes and times the
-// candidates once (see run_columns).  Shapes with one and with two rows per
+// nu = 30 also has a 640-thread shape (clusters up to 160 atoms, ten waves:
+// no idle waves in the dots and barriers for the 141-160-atom clusters of a
+// 6 A cutoff in diamond).  The library picks a shape per bucket of cluster
+// sizes and times every shape that holds the bucket once (see run_columns).  Shapes with one and with two rows per
 // thread add a thread's rows in a different grouping, so for nu = 40, 48 a
 // column's last bits depend on the plan chosen; every launch of a context
 // keeps its plans.
@@ -647,6 +649,7 @@ static const KrylovShapeInfo kShapes[] = {
     {40, 256, 2, nullptr}, {40, 512, 2, nullptr},
     {48, 256, 2, nullptr}, {48, 512, 2, nullptr},
     {40, 768, 1, nullptr}, {48, 768, 1, nullptr},
+    {30, 640, 1, nullptr},
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -667,6 +670,7 @@ static const void* shape_fn(int id) {
     case 12: return kfn<48, 2, 512>();
     case 13: return kfn<40, 1, 768>();
     case 14: return kfn<48, 1, 768>();
+    case 15: return kfn<30, 1, 640>();
     default: return nullptr;
   }
 }

@@ -111,6 +111,7 @@ struct KrylovPlan {
   int per_cu = 1;          // persistent workgroups per CU
   bool tuned = false;      // timed against the other candidates
   double us_per_col = 0.0; // measured time per column when tuned
+  int candidates = 0;      // plans timed (1: nothing to choose)
 };
 
 struct KrylovShapeInfo {

@@ -388,7 +388,11 @@ class Context:
     def stats(self):
         s = L.MagStats()
         self._check(self._lib.mag_get_stats(self._h, C.byref(s)))
-        return {name: getattr(s, name) for name, _ in L.MagStats._fields_}
+        out = {}
+        for name, _ in L.MagStats._fields_:
+            v = getattr(s, name)
+            out[name] = list(v) if isinstance(v, C.Array) else v
+        return out
 
 
 __all__ = ["Context", "MagError", "make_opts"]
