@@ -425,11 +425,11 @@ __device__ __forceinline__ bool ql_wave(const double* tr, int n, double* z, doub
 
 // ---------------------------------------------------------------------------
 // 3. eigenvectors, spectral weights and pattern rows.  One wave per column,
-// lane k carries eigenvector k.  Everything this kernel reads of the column
-// (rotation record, reflectors, L, the rows of Q) was written by earlier
-// kernels and is the same for every lane, so it is read through the constant
-// address space: scalar loads into SGPRs that feed the FMAs directly, no LDS
-// staging and no cross-lane broadcasts.
+// lane k carries eigenvector k.  What this kernel reads of the column and
+// every lane needs (rotation record, reflectors, L) was written by earlier
+// kernels, so it is read through the constant address space: scalar loads
+// into SGPRs that feed the FMAs directly.  The pattern rows of Q, one per
+// lane, come by vector loads.
 typedef const __attribute__((address_space(4))) double kdouble;
 typedef const __attribute__((address_space(4))) int32_t kint;
 
@@ -572,22 +572,52 @@ __device__ __forceinline__ void vectors_column(const EigArgs& a, int64_t slot, d
   }
   if (lane == 0) a.nu_eff_out[oi] = n;
 
-  // ---- P = (Q_pat c) diag(d): row p, column rank(k)
+  // ---- P = (Q_pat c) diag(d): lanes over pattern rows.  c_k d_k goes to LDS
+  // (transposed: entry t of vector k at k * LD + t) with the ranks; each lane
+  // loads its own row of Q_pat (contiguous rows: coalesced vector loads) and
+  // forms its row of P from broadcast reads of the staged vectors
   if (a.P) {
+    double* Cd = T;                                  // NM x LD (the transposes are done)
+    int* rk = reinterpret_cast<int*>(ev + NM);       // NM ranks
+    __syncthreads();                                 // every lane has read T and ev
+    if (lane < NM) {
+#pragma unroll
+      for (int t = 0; t < NM; ++t) Cd[lane * LD + t] = (lane < n) ? y[t] * dk : 0.0;
+      rk[lane] = rank;
+    }
+    __syncthreads();
     const int np = a.npat[slot];
     const int64_t base = a.pmode ? a.rowptr[j] : slot * (int64_t)a.pat_stride;
-    kdouble* qp = (kdouble*)(a.qpat + slot * (int64_t)a.pat_stride * NM);
-    double* Prow = a.P + base * nuo + rank;
-#pragma unroll 2
-    for (int p = 0; p < np; ++p) {
-      kdouble* qrow = qp + p * NM;
-      double y0 = 0.0, y1 = 0.0;
+    const double* qp = a.qpat + slot * (int64_t)a.pat_stride * NM;
+    for (int p0 = 0; p0 < np; p0 += ETPB) {
+      const int p = p0 + lane;
+      const bool row = p < np;
+      double q[NM];
+      const double* qr = qp + (int64_t)(row ? p : 0) * NM;
 #pragma unroll
       for (int t = 0; t < NM; t += 2) {
-        y0 = fma(qrow[t], y[t], y0);
-        if (t + 1 < NM) y1 = fma(qrow[t + 1], y[t + 1], y1);
+        if (t + 1 < NM) {
+          const double2 v = *reinterpret_cast<const double2*>(qr + t);
+          q[t] = v.x;
+          q[t + 1] = v.y;
+        } else {
+          q[t] = qr[t];
+        }
       }
-      if (lane < nuo) Prow[(int64_t)p * nuo] = (lane < n) ? (y0 + y1) * dk : 0.0;
+      double* Pr = a.P + (base + (row ? p : 0)) * nuo;
+#pragma unroll
+      for (int k = 0; k < NM; ++k) {
+        if (k < nuo) {
+          const double* ck = Cd + k * LD;
+          double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+          for (int t = 0; t < NM; t += 2) {
+            y0 = fma(q[t], ck[t], y0);
+            if (t + 1 < NM) y1 = fma(q[t + 1], ck[t + 1], y1);
+          }
+          if (row) Pr[rk[k]] = y0 + y1;
+        }
+      }
     }
   }
 }
@@ -616,7 +646,7 @@ template <int NM>
 static hipError_t launch_eig_nm(const EigArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)a.ncols;
   const size_t lds1 = (size_t)NM * (NM + 1) * sizeof(double);
-  const size_t lds3 = (size_t)NM * (NM + 1) * sizeof(double) + NM * sizeof(double);
+  const size_t lds3 = (size_t)NM * (NM + 1) * sizeof(double) + NM * sizeof(double) + NM * sizeof(int);
   hipLaunchKernelGGL(tri_kernel<NM>, dim3(nb), dim3(ETPB), lds1, s, a);
   hipError_t e = launch_fill_i32(a.fb_count, 1, 0, s);
   if (e != hipSuccess) return e;
