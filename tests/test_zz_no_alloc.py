@@ -4,6 +4,7 @@ calls in a row, the second on a smaller pattern (the fixed scratch keeps the
 first call's larger contents), no device memory taken by the call, and the
 documented rejections."""
 import ctypes as C
+import gc
 
 import numpy as np
 import pytest
@@ -28,13 +29,16 @@ def _compare(ctx, s, seed):
     pos, gH, gS = _inputs(ctx, s, seed)
     ref = ctx.sk_vjp(pos, gH, gS)
     out = torch.full((s.n_atoms, 3), float("nan"), dtype=torch.float64, device="cuda")
+    gc.collect()  # garbage of earlier tests freed now, not during the call
     torch.cuda.synchronize()
     held = ctx.stats()["device_bytes"]
+    torch.cuda.reset_peak_memory_stats()
     taken = torch.cuda.memory_allocated()
     ctx.sk_vjp_noalloc(pos, gH, gS, out)
     torch.cuda.synchronize()
+    # neither the library's own device memory nor torch's grew during the call
     assert ctx.stats()["device_bytes"] == held
-    assert torch.cuda.memory_allocated() == taken
+    assert torch.cuda.max_memory_allocated() == taken
     same = bool(torch.equal(out, ref))
     log(f"[noalloc] {s.n_atoms} atoms, {ctx.sk_nnz // 16} blocks: bitwise equal {same}, "
         f"max |grad| {ref.abs().max().item():.3e}")
