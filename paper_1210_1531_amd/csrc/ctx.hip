@@ -900,9 +900,9 @@ int mag_sk_build(mag_ctx* ctx, const mag_sk_model* model, int64_t n_atoms, const
   HIPCHK(launch_check_finite(ctx->sk_pos.as<double>(), 3 * n, ctx->errflag.as<int32_t>(),
                              ctx->stream));
   TRY(take_errors(ctx, "mag_sk_build"));
-  CellList cl;
+  CellList& cl = ctx->sk_cells;
   HIPCHK(build_cell_list(cl, ctx->sk_pos.as<double>(), n, cell, model->r_cut, ctx->stream));
-  DevBuf cnt;
+  DevBuf& cnt = ctx->sk_cnt;
   ALLOC(cnt, sizeof(int32_t) * n);
   HIPCHK(launch_sk_count(ctx->sk_pos.as<double>(), n, cell, model->r_cut, cl, cnt.as<int32_t>(),
                          ctx->errflag.as<int32_t>(), ctx->stream));
@@ -1134,7 +1134,6 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
   HIPCHK(launch_block_transpose(ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(), N,
                                 ctx->btrans.as<int32_t>(), ctx->errflag.as<int32_t>(),
                                 ctx->stream));
-  TRY(take_errors(ctx, "mag_set_system"));
 
   for (int d = 0; d < 3; ++d) ctx->cell[d] = sys->cell[d];
   ctx->r_cluster = sys->r_cluster;
@@ -1143,11 +1142,12 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
     TRY(copy_in(ctx, ctx->pos, sys->pos, sizeof(double) * 3 * N, mem_kind));
     HIPCHK(launch_check_finite(ctx->pos.as<double>(), 3 * N, ctx->errflag.as<int32_t>(),
                                ctx->stream));
-    TRY(take_errors(ctx, "mag_set_system"));
   }
+  TRY(take_errors(ctx, "mag_set_system"));  // the transpose's and the positions' checks
 
   // clusters
   std::vector<int64_t> cptr(N + 1);
+  std::vector<double> hp;  // positions on the host for the column order, when copied early
   if (sys->clus_ptr && sys->clus_atoms) {
     HIPCHK(hipMemcpyAsync(cptr.data(), sys->clus_ptr, sizeof(int64_t) * (N + 1),
                           mem_kind == MAG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
@@ -1188,9 +1188,10 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
     TRY(sync(ctx));
   } else {
     if (!ctx->has_pos) return fail(ctx, MAG_EINVAL, "clusters need pos (or clus_ptr/clus_atoms)");
-    CellList cl;
+    CellList& cl = ctx->sys_cells;
     HIPCHK(build_cell_list(cl, ctx->pos.as<double>(), N, sys->cell, sys->r_cluster, ctx->stream));
-    DevBuf tmp, cnt;
+    DevBuf& tmp = ctx->sys_tmp;
+    DevBuf& cnt = ctx->sys_cnt;
     ALLOC(tmp, sizeof(int32_t) * N * (size_t)CLUSTER_MAX);
     ALLOC(cnt, sizeof(int32_t) * N);
     HIPCHK(launch_cluster_scan_cv(ctx->pos.as<double>(), N, sys->cell, sys->r_cluster, cl,
@@ -1199,6 +1200,11 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
     std::vector<int32_t> hc(N);
     HIPCHK(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost,
                           ctx->stream));
+    if (mem_kind == MAG_DEVICE) {  // the column order needs them: one round trip for both
+      hp.resize(3 * N);
+      HIPCHK(hipMemcpyAsync(hp.data(), ctx->pos.p, sizeof(double) * 3 * N, hipMemcpyDeviceToHost,
+                            ctx->stream));
+    }
     TRY(take_errors(ctx, "cluster build"));
     cptr[0] = 0;
     for (int64_t J = 0; J < N; ++J) cptr[J + 1] = cptr[J] + hc[J];
@@ -1216,7 +1222,7 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
     maxc = std::max<int64_t>(maxc, ctx->h_clus_size[J]);
   }
   {
-    DevBuf nz;
+    DevBuf& nz = ctx->sys_nz;
     ALLOC(nz, sizeof(int64_t) * N);
     HIPCHK(launch_cluster_nnz(ctx->bptr.as<int32_t>(), ctx->bcol.as<int32_t>(),
                               ctx->clus_ptr.as<int64_t>(), ctx->clus_atoms.as<int32_t>(), N,
@@ -1249,10 +1255,12 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
     std::stable_sort(atoms.begin(), atoms.end(),
                      [&](int32_t a, int32_t b) { return key[a] < key[b]; });
   } else if (ctx->has_pos) {
-    std::vector<double> hp(3 * N);
-    HIPCHK(hipMemcpyAsync(hp.data(), ctx->pos.p, sizeof(double) * 3 * N, hipMemcpyDeviceToHost,
-                          ctx->stream));
-    TRY(sync(ctx));
+    if (hp.size() != (size_t)(3 * N)) {
+      hp.resize(3 * N);
+      HIPCHK(hipMemcpyAsync(hp.data(), ctx->pos.p, sizeof(double) * 3 * N, hipMemcpyDeviceToHost,
+                            ctx->stream));
+      TRY(sync(ctx));
+    }
     std::vector<uint64_t> key(N);
     for (int64_t i = 0; i < N; ++i) {
       uint64_t code = 0;

@@ -356,6 +356,9 @@ struct mag_ctx {
   mag::DevBuf md_x, md_v, md_F, md_Frep, md_e, md_sum;  // MD step state
   mag::DevBuf f_part, f_grad;  // force contraction: per-block parts, per-atom sums
   mag::DevBuf adj_cvec, adj_cdg, adj_hbar, adj_wbar, adj_fJ, adj_F, adj_counter;  // exact gradient
+  // set-up scratch kept between calls (an MD frame rebuilds pattern and clusters)
+  mag::CellList sk_cells, sys_cells;
+  mag::DevBuf sk_cnt, sys_tmp, sys_cnt, sys_nz;
 
   // system
   bool has_system = false;
