@@ -17,9 +17,10 @@
 //     the diagonal), K_ab = D_ab d_a g_b gives (Daleckii-Krein)
 //       hbar = c (K + K^T) c^T,   sbar = -c (K Lambda + Lambda K^T) c^T
 //     (adj_prep_kernel);
-//  2. the Krylov basis is grown again exactly as in the forward pass (basis
-//     in registers), then the recurrence q_{k+1} = (H q_k - Q_k t_k) / beta_k
-//     is run backwards.  The adjoint of every step needs only the next basis
+//  2. the forward pass leaves each column's basis Q, its h, the beta_k and the
+//     last step's residual in scratch; they are loaded back into registers
+//     (the basis as the forward holds it), and the recurrence
+//     q_{k+1} = (H q_k - Q_k t_k) / beta_k is run backwards.  The adjoint of every step needs only the next basis
 //     vector's adjoint qbar_{k+1}:
 //       rbar_k = (1 - q_{k+1} q_{k+1}^T) qbar_{k+1} / beta_k,
 //       wbar_k = (1 - Q_{k+1} Q_{k+1}^T) qbar_{k+1} / beta_k,  Hbar += wbar_k q_k^T,
@@ -395,121 +396,33 @@ __global__ __launch_bounds__(KTPB) void adjoint_kernel(AdjointArgs a) {
 
     for (int alpha = 0; alpha < NORB; ++alpha) {
       const int64_t slot = 4 * ia + alpha;
-      const int ell = NORB * jl + alpha;
-      // ---- forward: the Krylov basis again, as the forward pass grows it
-      for (int i = tid; i < nC; i += KTPB) s_x[i] = (i == ell) ? 1.0 : 0.0;
+      // ---- the forward pass's Krylov data of this column: its basis (in
+      // registers, as the forward holds it), h, beta and the last residual
+      const int n = a.nu_eff[slot];
+      if (n < 1 || n > NU) continue;  // a failed column (the forward flagged it)
       double qv[R][NU];
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-#pragma unroll
-        for (int i = 0; i < NU; ++i) qv[rr][i] = 0.0;
-        if (R * tid + rr == ell) qv[rr][0] = 1.0;
-      }
       double rlast[R];
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) rlast[rr] = 0.0;
-      const int nu_max = min(a.nu, nC);
-      int nu_eff = nu_max;
-      __syncthreads();
-      for (int k = 0; k < nu_max; ++k) {
-        double w[R];
+      {
+        const double* qg = a.q + slot * (int64_t)cap * a.qrows;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
-          double sy;
-          row_spmv<false>(rowp[rr], s_ent, e_beg[rr], e_end[rr], s_x, s_x, w[rr], sy);
+          const int r = R * tid + rr;
+          const bool in = r < nC;
+#pragma unroll
+          for (int k = 0; k < NU; ++k)
+            qv[rr][k] = (in && k < n) ? qg[(int64_t)k * a.qrows + r] : 0.0;
+          rlast[rr] = in ? a.r[slot * (int64_t)a.qrows + r] : 0.0;
         }
-        const int kc = k >> 3;
-        basis_dots<NU, R, KTPB, true>(qv, w, kc, s_red, s_fin);
-        const double ww1 = s_fin[8 * NCH];
-        for (int i = tid; i <= k; i += KTPB) {
-          s_h[i * NU + k] = s_fin[i];
-          s_h[k * NU + i] = s_fin[i];
+        const double* hg = a.h + slot * (int64_t)cap * cap;
+        for (int idx = tid; idx < NU * NU; idx += KTPB) {
+          const int i = idx / NU, k = idx - (idx / NU) * NU;
+          const int lo = min(i, k), hi = max(i, k);
+          s_h[idx] = (i < n && k < n) ? hg[(int64_t)hi * cap + lo] : 0.0;
         }
-        bool go = (k + 1 < nu_max);
-        if (!isfinite(ww1)) {
-          if (tid == 0) atomicOr(a.err, (int)KERR_NONFINITE);
-          nu_eff = k + 1;
-          go = false;
-        }
-        // w -= Q h[:, k]
-        double hsq = 0.0;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          if (c <= kc) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int i = c * 8 + t;
-              if (i < NU) {
-                const double hi = s_fin[c * 8 + t];
-                hsq = fma(hi, hi, hsq);
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], hi, w[rr]);
-              }
-            }
-          }
-        }
-        if (!go) {
-          // residual of the last step: H q_n - Q h[:, n-1]
-#pragma unroll
-          for (int rr = 0; rr < R; ++rr) rlast[rr] = w[rr];
-        } else {
-          double beta2 = ww1 - hsq;
-          if (!(beta2 > 0.5 * ww1)) {
-            basis_dots<NU, R, KTPB, true>(qv, w, kc, s_red, s_fin);
-            double csq = 0.0;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-              if (c <= kc) {
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                  const int i = c * 8 + t;
-                  if (i < NU) {
-                    const double ci = s_fin[c * 8 + t];
-                    csq = fma(ci, ci, csq);
-#pragma unroll
-                    for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], ci, w[rr]);
-                  }
-                }
-              }
-            }
-            beta2 = s_fin[8 * NCH] - csq;
-            if (!(beta2 > 0.5 * s_fin[8 * NCH])) {
-              double dummy[R];
-#pragma unroll
-              for (int rr = 0; rr < R; ++rr) dummy[rr] = w[rr];
-              basis_dots<NU, R, KTPB, true>(qv, dummy, -1, s_red, s_fin);
-              beta2 = s_fin[8 * NCH];
-            }
-          }
-          const double b2 = fmax(beta2, 0.0);
-          if (!(b2 > a.breakdown * a.breakdown * ww1)) {
-            // invariant space: the residual is (numerically) zero
-            nu_eff = k + 1;
-            go = false;
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) rlast[rr] = w[rr];
-          } else {
-            const double inv = rsqrt(b2);
-            if (tid == 0) s_beta[k] = sqrt(b2);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
-            store_column<NU, R>(qv, w, k + 1);
-            __syncthreads();  // every thread has read s_x in its SpMV
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-              const int r = R * tid + rr;
-              if (r < nC) s_x[r] = w[rr];
-            }
-          }
-        }
-        __syncthreads();
-        if (!go) break;
+        for (int k = tid; k < NU; k += KTPB)
+          s_beta[k] = (k + 1 < n) ? a.beta[slot * (int64_t)cap + k] : 0.0;
       }
-      const int n = nu_eff;
-      if (n != a.nu_eff[slot]) {
-        if (tid == 0) atomicOr(a.err, (int)KERR_PATTERN);
-        continue;
-      }
+      __syncthreads();
 
       // ---- the projected adjoints and the sweep's small matrices
       const double* hb_g = a.hbar + slot * (int64_t)(2 * cap * cap);

@@ -234,7 +234,9 @@ int64_t chunk_columns(const ColumnJob& job, int64_t n) {
       sizeof(double) * ((size_t)5 * cap + 2 * (size_t)rec_cap) +
       sizeof(int32_t) * ((size_t)sweep_cap + 2) +
       (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0) +
-      (job.consumer == 4 ? sizeof(double) * ((size_t)3 * cap * cap + 3 * cap) : 0);
+      (job.consumer == 4 ? sizeof(double) * ((size_t)4 * cap * cap + 4 * cap +
+                                             (size_t)(cap + 1) * NC_MAX)
+                         : 0);
   const char* env = std::getenv("MAG_SCRATCH_GB");
   const double budget_gb = env ? std::atof(env) : 8.0;
   int64_t bmax = (int64_t)(budget_gb * 1e9 / (double)per_slot);
@@ -470,6 +472,10 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
     ALLOC(ctx->adj_cvec, sizeof(double) * bsz * cap * cap);
     ALLOC(ctx->adj_cdg, sizeof(double) * bsz * 3 * cap);
     ALLOC(ctx->adj_hbar, sizeof(double) * bsz * 2 * cap * cap);
+    ALLOC(ctx->adj_q, sizeof(double) * bsz * cap * (size_t)NC_MAX);
+    ALLOC(ctx->adj_r, sizeof(double) * bsz * (size_t)NC_MAX);
+    ALLOC(ctx->adj_h, sizeof(double) * bsz * cap * cap);
+    ALLOC(ctx->adj_beta, sizeof(double) * bsz * cap);
   }
   double* Pbuf = job.P_store;
   if (job.want_P && !job.P_store) {
@@ -518,6 +524,13 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
     ka.full = job.full;
     ka.cache_cap = 0;
     ka.slots = nullptr;
+    if (job.consumer == 4) {  // the exact gradient reads the forward's basis back
+      ka.adj_q = ctx->adj_q.as<double>();
+      ka.adj_r = ctx->adj_r.as<double>();
+      ka.adj_h = ctx->adj_h.as<double>();
+      ka.adj_beta = ctx->adj_beta.as<double>();
+      ka.adj_rows = NC_MAX;
+    }
 
     EigArgs ea{};
     ea.hs = ka.hs;
@@ -560,6 +573,12 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
         k1.qpat = ka.qpat + q * (int64_t)pat_stride * cap;
         k1.nu_eff = ka.nu_eff + q;
         k1.npat = ka.npat + q;
+        if (ka.adj_q) {
+          k1.adj_q = ka.adj_q + q * (int64_t)cap * NC_MAX;
+          k1.adj_r = ka.adj_r + q * (int64_t)NC_MAX;
+          k1.adj_h = ka.adj_h + q * (int64_t)cap * cap;
+          k1.adj_beta = ka.adj_beta + q * (int64_t)cap;
+        }
         const KrylovPlan& pl = krylov_plan(ctx, shapes, bucket[i0 + q], ncu);
         k1.cache_cap = pl.cache;
         HIPCHK(launch_krylov(k1, pl.shape, pl.dyn, 1, ctx->stream));
@@ -694,6 +713,11 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
       aa.counter = ctx->adj_counter.as<int32_t>();
       aa.err = ka.err;
       aa.cap = cap;
+      aa.q = ctx->adj_q.as<double>();
+      aa.r = ctx->adj_r.as<double>();
+      aa.h = ctx->adj_h.as<double>();
+      aa.beta = ctx->adj_beta.as<double>();
+      aa.qrows = NC_MAX;
       HIPCHK(launch_adjoint(aa, grid, ctx->stream));
     }
     if (job.consumer == 2) {
@@ -2130,8 +2154,15 @@ int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
                           &ctx->tmp_out, &ctx->k_trid, &ctx->k_evu, &ctx->k_rot,
                           &ctx->k_sweep, &ctx->k_qlst, &ctx->k_fbl, &ctx->k_fbc,
                           &ctx->md_x, &ctx->md_v, &ctx->md_F, &ctx->md_Frep, &ctx->md_e,
-                          &ctx->md_sum, &ctx->f_part, &ctx->f_grad};
+                          &ctx->md_sum, &ctx->f_part, &ctx->f_grad, &ctx->k_slots,
+                          &ctx->k_qbeg, &ctx->adj_cvec, &ctx->adj_cdg, &ctx->adj_hbar,
+                          &ctx->adj_wbar, &ctx->adj_fJ, &ctx->adj_F, &ctx->adj_counter,
+                          &ctx->adj_q, &ctx->adj_r, &ctx->adj_h, &ctx->adj_beta, &ctx->sk_cnt,
+                          &ctx->sys_tmp, &ctx->sys_cnt, &ctx->sys_nz};
   for (const DevBuf* b : bufs) bytes += (int64_t)b->bytes;
+  for (const CellList* c : {&ctx->sk_cells, &ctx->sys_cells})
+    bytes += (int64_t)(c->cell_of.bytes + c->cell_count.bytes + c->cell_start.bytes +
+                       c->cell_atoms.bytes);
   ctx->stats.device_bytes = bytes;
   *out = ctx->stats;
   return MAG_OK;

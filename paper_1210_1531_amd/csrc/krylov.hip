@@ -108,7 +108,7 @@ __device__ __forceinline__ int lds_find(const int32_t* a, int n, int key) {
   zacc = fma(s23.x, x23.x, zacc);                           \
   zacc = fma(s23.y, x23.y, zacc);
 
-template <int NU, int R, int KTPB>
+template <int NU, int R, int KTPB, bool ADJ>
 __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
   constexpr int KWAVES = KTPB / 64;
   constexpr int NCH = (NU + 7) / 8;
@@ -449,16 +449,20 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
         for (int i = tid; i <= k; i += KTPB) {
           hcol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + (i & 7)];
           scol[(int64_t)k * cap + i] = s_fin[(i >> 3) * 16 + 8 + (i & 7)];
+          if (ADJ) a.adj_h[slot * (int64_t)cap * cap + (int64_t)k * cap + i] =
+              s_fin[(i >> 3) * 16 + (i & 7)];
         }
         // a single exit at the bottom of the step keeps the basis registers in
         // place (each early exit would need its own copy of them)
         bool go = (k + 1 < nu_max);
+        bool orth = false;  // w orthogonalized in this step
         if (!isfinite(ww1)) {
           if (tid == 0) atomicOr(a.err, (int)KERR_NONFINITE);
           nu_eff = k + 1;
           go = false;
         }
         if (go) {
+        orth = true;
 
         // ---- w -= Q h[:, k]; |h|^2 rides along (columns past k hold zeros)
         double hsq = 0.0;
@@ -561,6 +565,7 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           go = false;
         } else {
           const double inv = rsqrt(b2);
+          if (ADJ && tid == 0) a.adj_beta[slot * (int64_t)cap + k] = sqrt(b2);
 #pragma unroll
           for (int rr = 0; rr < R; ++rr) w[rr] *= inv;
           // q_{k+1} into its register column.  k is uniform, so each test is a
@@ -591,6 +596,31 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
           }
         }
         }
+        if (ADJ && !go) {
+          // the last step's residual H q_n - Q h[:, n-1] for the exact
+          // gradient (a breakdown step has already orthogonalized w)
+          if (!orth) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+              if (c <= kc) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                  const int i = c * 8 + t;
+                  if (i < NU) {
+                    const double hi = s_fin[c * 16 + t];
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr) w[rr] = fma(-qv[rr][i], hi, w[rr]);
+                  }
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) {
+            const int r = R * tid + rr;
+            if (r < a.adj_rows) a.adj_r[slot * (int64_t)a.adj_rows + r] = (r < nC) ? w[rr] : 0.0;
+          }
+        }
         __syncthreads();
         if (!go) break;
       }
@@ -618,6 +648,11 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             for (int i = NU; i < cap; ++i) dst[i] = 0.0;
           }
         }
+        if (ADJ && r < a.adj_rows) {
+          double* dq = a.adj_q + slot * (int64_t)cap * a.adj_rows + r;
+#pragma unroll
+          for (int i = 0; i < NU; ++i) dq[(int64_t)i * a.adj_rows] = (r < nC) ? qv[rr][i] : 0.0;
+        }
       }
       __syncthreads();
     }
@@ -638,8 +673,9 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
 // column's last bits depend on the plan chosen; every launch of a context
 // keeps its plans.
 template <int NU, int R, int T>
-static const void* kfn() {
-  return reinterpret_cast<const void*>(&krylov_kernel<NU, R, T>);
+static const void* kfn(bool adj) {
+  return adj ? reinterpret_cast<const void*>(&krylov_kernel<NU, R, T, true>)
+             : reinterpret_cast<const void*>(&krylov_kernel<NU, R, T, false>);
 }
 
 static const KrylovShapeInfo kShapes[] = {
@@ -653,24 +689,26 @@ static const KrylovShapeInfo kShapes[] = {
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
-static const void* shape_fn(int id) {
+// the kernel of shape `id`; adj: the variant that also leaves each column's
+// basis, h, beta and last residual for the exact gradient (nu <= 30 shapes only)
+static const void* shape_fn(int id, bool adj = false) {
   switch (id) {
-    case 0: return kfn<12, 1, 256>();
-    case 1: return kfn<12, 1, 512>();
-    case 2: return kfn<12, 1, 768>();
-    case 3: return kfn<20, 1, 256>();
-    case 4: return kfn<20, 1, 512>();
-    case 5: return kfn<20, 1, 768>();
-    case 6: return kfn<30, 1, 256>();
-    case 7: return kfn<30, 1, 512>();
-    case 8: return kfn<30, 1, 768>();
-    case 9: return kfn<40, 2, 256>();
-    case 10: return kfn<40, 2, 512>();
-    case 11: return kfn<48, 2, 256>();
-    case 12: return kfn<48, 2, 512>();
-    case 13: return kfn<40, 1, 768>();
-    case 14: return kfn<48, 1, 768>();
-    case 15: return kfn<30, 1, 640>();
+    case 0: return kfn<12, 1, 256>(adj);
+    case 1: return kfn<12, 1, 512>(adj);
+    case 2: return kfn<12, 1, 768>(adj);
+    case 3: return kfn<20, 1, 256>(adj);
+    case 4: return kfn<20, 1, 512>(adj);
+    case 5: return kfn<20, 1, 768>(adj);
+    case 6: return kfn<30, 1, 256>(adj);
+    case 7: return kfn<30, 1, 512>(adj);
+    case 8: return kfn<30, 1, 768>(adj);
+    case 9: return adj ? nullptr : kfn<40, 2, 256>(false);
+    case 10: return adj ? nullptr : kfn<40, 2, 512>(false);
+    case 11: return adj ? nullptr : kfn<48, 2, 256>(false);
+    case 12: return adj ? nullptr : kfn<48, 2, 512>(false);
+    case 13: return adj ? nullptr : kfn<40, 1, 768>(false);
+    case 14: return adj ? nullptr : kfn<48, 1, 768>(false);
+    case 15: return kfn<30, 1, 640>(adj);
     default: return nullptr;
   }
 }
@@ -717,6 +755,13 @@ int krylov_occupancy(int id, size_t dyn) {
       (void)hipGetLastError();
       return 0;
     }
+    // the exact-gradient variant launches with the same plans
+    const void* fa = shape_fn(id, true);
+    if (fa && hipFuncSetAttribute(fa, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) !=
+                  hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
     dyn_set[id] = dyn;
   }
   int nb = 0;
@@ -728,7 +773,7 @@ int krylov_occupancy(int id, size_t dyn) {
 }
 
 hipError_t launch_krylov(const KrylovArgs& a, int id, size_t dyn, int grid, hipStream_t s) {
-  const void* fn = shape_fn(id);
+  const void* fn = shape_fn(id, a.adj_q != nullptr);
   if (!fn || grid <= 0) return hipErrorInvalidValue;
   KrylovArgs copy = a;
   void* args[] = {&copy};

@@ -101,6 +101,15 @@ struct KrylovArgs {
   int full;                // 1: write every cluster row of Q, not only the pattern
   int cache_cap;           // cluster blocks kept in LDS for the whole column (dynamic LDS)
   const int32_t* slots;    // nullptr: list position = slot; else the slots of this launch
+  // for the exact gradient (or nullptr): per slot the whole basis (cap columns
+  // of adj_rows rows, column k at k * adj_rows), the last step's residual
+  // H q_n - Q h[:, n-1] (adj_rows), h (cap x cap, column k rows i <= k) and
+  // beta_k (cap)
+  double* adj_q;
+  double* adj_r;
+  double* adj_h;
+  double* adj_beta;
+  int adj_rows;
 };
 
 // how the Krylov columns of one bucket of cluster sizes are launched
@@ -248,6 +257,13 @@ struct AdjointArgs {
   int32_t* counter;        // atom counter of the persistent workgroups
   int32_t* err;
   int cap;
+  // the forward pass's basis, last residual, h and beta per slot (layouts as
+  // the Krylov kernel's adj_* outputs)
+  const double* q;
+  const double* r;
+  const double* h;
+  const double* beta;
+  int qrows;
 };
 int adjoint_supported(int cap);
 size_t adjoint_dyn_lds(int cap);
@@ -356,6 +372,7 @@ struct mag_ctx {
   mag::DevBuf md_x, md_v, md_F, md_Frep, md_e, md_sum;  // MD step state
   mag::DevBuf f_part, f_grad;  // force contraction: per-block parts, per-atom sums
   mag::DevBuf adj_cvec, adj_cdg, adj_hbar, adj_wbar, adj_fJ, adj_F, adj_counter;  // exact gradient
+  mag::DevBuf adj_q, adj_r, adj_h, adj_beta;  // the forward pass's Krylov data for it
   // set-up scratch kept between calls (an MD frame rebuilds pattern and clusters)
   mag::CellList sk_cells, sys_cells;
   mag::DevBuf sk_cnt, sys_tmp, sys_cnt, sys_nz;
