@@ -235,11 +235,15 @@ typedef struct {
   int eig_sweeps;     /* QL sweeps recorded per column (<= 0: the library's cap, 4 nu up
                          to 128); a column that needs more is finished by the one-wave
                          QL that applies its rotations directly (same results to rounding) */
+  int keep_exact;     /* 1: pass 1 keeps each column's Krylov basis, h, beta, last residual
+                         and Ritz vectors (about (nu + 1) 768 + 4 nu^2 doubles per column) so
+                         that a following mag_forces_exact skips its own pass; kept only
+                         when every column fits one chunk (MAG_SCRATCH_GB) and nu <= 30 */
 } mag_opts;
 
 /* Fill opts with the defaults (nu 30, kT 0.1, n_electrons 0 (must be set),
  * mu_tol 1e-12, mu_fixed NaN, breakdown 1e-12, workflow AUTO, schedule AUTO,
- * eig_sweeps 0). */
+ * eig_sweeps 0, keep_exact 0). */
 void mag_opts_default(mag_opts* opts);
 
 /* Pass 1 of Eq. 3 over every column, then mu, then the energies.

@@ -72,6 +72,7 @@ class MagOpts(C.Structure):
         ("workflow", C.c_int),
         ("schedule", C.c_int),
         ("eig_sweeps", C.c_int),
+        ("keep_exact", C.c_int),
     ]
 
 

@@ -181,6 +181,7 @@ struct ColumnJob {
   int nu = 30;
   double breakdown = 1e-12;
   int eig_sweeps = 0;      // > 0: fewer recorded QL sweeps than the buffers hold
+  int keep_adj = 0;        // pass 1 of a solve that keeps the exact gradient's inputs
   int schedule = MAG_SCHED_AUTO;
   int full = 0;            // write every cluster row of Q
   // eig outputs
@@ -234,7 +235,7 @@ int64_t chunk_columns(const ColumnJob& job, int64_t n) {
       sizeof(double) * ((size_t)5 * cap + 2 * (size_t)rec_cap) +
       sizeof(int32_t) * ((size_t)sweep_cap + 2) +
       (job.want_P && !job.P_store ? sizeof(double) * (size_t)pat_stride * job.nu : 0) +
-      (job.consumer == 4 ? sizeof(double) * ((size_t)4 * cap * cap + 4 * cap +
+      (job.consumer == 4 || job.keep_adj ? sizeof(double) * ((size_t)4 * cap * cap + 4 * cap +
                                              (size_t)(cap + 1) * NC_MAX)
                          : 0);
   const char* env = std::getenv("MAG_SCRATCH_GB");
@@ -449,6 +450,48 @@ static void record_plans(mag_ctx* ctx, const std::vector<KrylovShapeInfo>& shape
   }
 }
 
+// the exact gradient of one chunk of whole atoms whose pass-1 data (Ritz
+// vectors, basis, h, beta, last residual) are in the adj_* buffers: the
+// pencil's adjoint, the reverse sweep with the contraction, per-atom parts
+static int adjoint_tail(mag_ctx* ctx, const ColumnJob& job, const int32_t* cols,
+                        const int32_t* nu_eff, int64_t cnt, int cap, int ncu) {
+  HIPCHK(launch_adj_prep(ctx->adj_cvec.as<double>(), ctx->adj_cdg.as<double>(), nu_eff, cnt, cap,
+                         ctx->state.as<MuState>(), ctx->adj_hbar.as<double>(), ctx->stream));
+  const int occ = std::max(1, adjoint_occupancy(cap));
+  const int64_t natoms = cnt / NORB;
+  const int grid = (int)std::min<int64_t>(natoms, (int64_t)ncu * occ);
+  ALLOC(ctx->adj_wbar, adjoint_scratch_per_wg(cap) * (size_t)grid);
+  ALLOC(ctx->adj_counter, sizeof(int32_t));
+  HIPCHK(launch_fill_i32(ctx->adj_counter.as<int32_t>(), 1, 0, ctx->stream));
+  AdjointArgs aa{};
+  aa.bptr = ctx->bptr.as<int32_t>();
+  aa.bcol = ctx->bcol.as<int32_t>();
+  aa.bval = ctx->bval.as<double>();
+  aa.clus_ptr = ctx->clus_ptr.as<int64_t>();
+  aa.clus_atoms = ctx->clus_atoms.as<int32_t>();
+  aa.pos = ctx->pos.as<double>();
+  for (int d = 0; d < 3; ++d) aa.box[d] = ctx->cell[d];
+  aa.m = job.skm;
+  aa.cols = cols;
+  aa.natoms = natoms;
+  aa.nu = job.nu;
+  aa.breakdown = job.breakdown;
+  aa.hbar = ctx->adj_hbar.as<double>();
+  aa.nu_eff = nu_eff;
+  aa.wbar = ctx->adj_wbar.as<double>();
+  aa.fJ = ctx->adj_fJ.as<double>();
+  aa.counter = ctx->adj_counter.as<int32_t>();
+  aa.err = ctx->errflag.as<int32_t>();
+  aa.cap = cap;
+  aa.q = ctx->adj_q.as<double>();
+  aa.r = ctx->adj_r.as<double>();
+  aa.h = ctx->adj_h.as<double>();
+  aa.beta = ctx->adj_beta.as<double>();
+  aa.qrows = NC_MAX;
+  HIPCHK(launch_adjoint(aa, grid, ctx->stream));
+  return MAG_OK;
+}
+
 int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
   const int64_t n = (int64_t)job.cols_host.size();
   if (n == 0) return MAG_OK;
@@ -468,7 +511,8 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
   ALLOC(ctx->k_qlst, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_fbl, sizeof(int32_t) * bsz);
   ALLOC(ctx->k_fbc, sizeof(int32_t));
-  if (job.consumer == 4) {
+  const bool adj_out = job.consumer == 4 || job.keep_adj;
+  if (adj_out) {
     ALLOC(ctx->adj_cvec, sizeof(double) * bsz * cap * cap);
     ALLOC(ctx->adj_cdg, sizeof(double) * bsz * 3 * cap);
     ALLOC(ctx->adj_hbar, sizeof(double) * bsz * 2 * cap * cap);
@@ -524,7 +568,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
     ka.full = job.full;
     ka.cache_cap = 0;
     ka.slots = nullptr;
-    if (job.consumer == 4) {  // the exact gradient reads the forward's basis back
+    if (adj_out) {  // the exact gradient reads the forward's basis back
       ka.adj_q = ctx->adj_q.as<double>();
       ka.adj_r = ctx->adj_r.as<double>();
       ka.adj_h = ctx->adj_h.as<double>();
@@ -560,8 +604,8 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
     ea.fb_count = ctx->k_fbc.as<int32_t>();
     ea.rec_cap = rec_cap;
     ea.sweep_cap = job.eig_sweeps > 0 ? std::min(job.eig_sweeps, sweep_cap) : sweep_cap;
-    ea.cvec = job.consumer == 4 ? ctx->adj_cvec.as<double>() : nullptr;
-    ea.cdg = job.consumer == 4 ? ctx->adj_cdg.as<double>() : nullptr;
+    ea.cvec = adj_out ? ctx->adj_cvec.as<double>() : nullptr;
+    ea.cdg = adj_out ? ctx->adj_cdg.as<double>() : nullptr;
 
     if (schedule == MAG_SCHED_PLAIN) {
       for (int64_t q = 0; q < cnt; ++q) {
@@ -683,43 +727,7 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
       }
     }
 
-    if (job.consumer == 4) {
-      HIPCHK(launch_adj_prep(ctx->adj_cvec.as<double>(), ctx->adj_cdg.as<double>(), ka.nu_eff, cnt,
-                             cap, ctx->state.as<MuState>(), ctx->adj_hbar.as<double>(),
-                             ctx->stream));
-      const int occ = std::max(1, adjoint_occupancy(cap));
-      const int64_t natoms = cnt / NORB;
-      const int grid = (int)std::min<int64_t>(natoms, (int64_t)ncu * occ);
-      ALLOC(ctx->adj_wbar, adjoint_scratch_per_wg(cap) * (size_t)grid);
-      ALLOC(ctx->adj_counter, sizeof(int32_t));
-      HIPCHK(launch_fill_i32(ctx->adj_counter.as<int32_t>(), 1, 0, ctx->stream));
-      AdjointArgs aa{};
-      aa.bptr = ka.bptr;
-      aa.bcol = ka.bcol;
-      aa.bval = ka.bval;
-      aa.clus_ptr = ka.clus_ptr;
-      aa.clus_atoms = ka.clus_atoms;
-      aa.pos = ctx->pos.as<double>();
-      for (int d = 0; d < 3; ++d) aa.box[d] = ctx->cell[d];
-      aa.m = job.skm;
-      aa.cols = ka.cols;
-      aa.natoms = natoms;
-      aa.nu = job.nu;
-      aa.breakdown = job.breakdown;
-      aa.hbar = ctx->adj_hbar.as<double>();
-      aa.nu_eff = ka.nu_eff;
-      aa.wbar = ctx->adj_wbar.as<double>();
-      aa.fJ = ctx->adj_fJ.as<double>();
-      aa.counter = ctx->adj_counter.as<int32_t>();
-      aa.err = ka.err;
-      aa.cap = cap;
-      aa.q = ctx->adj_q.as<double>();
-      aa.r = ctx->adj_r.as<double>();
-      aa.h = ctx->adj_h.as<double>();
-      aa.beta = ctx->adj_beta.as<double>();
-      aa.qrows = NC_MAX;
-      HIPCHK(launch_adjoint(aa, grid, ctx->stream));
-    }
+    if (job.consumer == 4) TRY(adjoint_tail(ctx, job, ka.cols, ka.nu_eff, cnt, cap, ncu));
     if (job.consumer == 2) {
       HIPCHK(launch_cluster_rho(Pbuf, pat_stride, ka.cols, cnt, ka.npat, job.out_off + i0,
                                 job.eps + i0 * job.nu, job.nu_eff + i0, job.nu,
@@ -746,6 +754,14 @@ int run_columns(mag_ctx* ctx, ColumnJob& job, const GraphLists* gl = nullptr) {
       HIPCHK(launch_density(da, ctx->stream));
     }
     // the next chunk reuses the scratch: stream order keeps it safe
+  }
+  if (job.keep_adj && bsz >= n) {
+    // one chunk held every column: its exact-gradient inputs stay for
+    // mag_forces_exact (the column dimensions with them)
+    ALLOC(ctx->adj_nu, sizeof(int32_t) * n);
+    HIPCHK(hipMemcpyAsync(ctx->adj_nu.p, ctx->k_nu.p, sizeof(int32_t) * n,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->adj_kept = true;
   }
   if (ctx->time_kernels) {
     TRY(sync(ctx));
@@ -776,6 +792,8 @@ int check_opts(mag_ctx* ctx, const mag_opts* o) {
     return fail(ctx, MAG_EINVAL, "unknown schedule");
   if (!std::isnan(o->mu_fixed) && !std::isfinite(o->mu_fixed))
     return fail(ctx, MAG_EINVAL, "mu_fixed must be finite or NaN");
+  if (o->keep_exact != 0 && o->keep_exact != 1)
+    return fail(ctx, MAG_EINVAL, "keep_exact must be 0 or 1");
   return MAG_OK;
 }
 
@@ -901,6 +919,7 @@ void mag_opts_default(mag_opts* o) {
   o->workflow = MAG_WORKFLOW_AUTO;
   o->schedule = MAG_SCHED_AUTO;
   o->eig_sweeps = 0;
+  o->keep_exact = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,6 +1116,7 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
   ctx->has_system = false;
   ctx->solved = false;
   ctx->density_ready = false;
+  ctx->adj_kept = false;
   const int64_t N = sys->n_atoms, M = NORB * N, nnz = sys->nnz;
   if (M > (int64_t)INT32_MAX / 2)
     return fail(ctx, MAG_EUNSUPPORTED, "too many atoms for 32-bit column indices");
@@ -1323,6 +1343,7 @@ int mag_set_system(mag_ctx* ctx, const mag_system* sys, int mem_kind) {
 int mag_update_values(mag_ctx* ctx, const double* H, const double* S, int mem_kind) {
   TRY(ensure_system(ctx));
   TRY(check_mem_kind(ctx, mem_kind));
+  ctx->adj_kept = false;
   if (!H || !S) return fail(ctx, MAG_EINVAL, "H and S are required");
   DevBuf hv, sv;
   const double* phv = H;
@@ -1537,6 +1558,7 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
     return fail(ctx, MAG_EBRACKET, "n_electrons must lie in (0, 2M)");
   ctx->solved = false;
   ctx->density_ready = false;
+  ctx->adj_kept = false;
   ctx->opts = *opts;
   if (opts->workflow == MAG_WORKFLOW_AUTO) {
     size_t free_b = 0, total_b = 0;
@@ -1572,6 +1594,8 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
   job.nu_eff = ctx->nu_eff.as<int32_t>();
   job.want_P = store ? 1 : 0;
   job.P_store = store ? ctx->P.as<double>() : nullptr;
+  job.keep_adj = (opts->keep_exact && adjoint_supported(krylov_capacity(nu)) &&
+                  opts->schedule != MAG_SCHED_GRAPH) ? 1 : 0;
   ctx->time_kernels = true;
   ctx->stats.t_krylov_ms = 0.0;
   ctx->stats.t_eig_ms = 0.0;
@@ -1913,7 +1937,13 @@ int mag_forces_exact(mag_ctx* ctx, const mag_sk_model* model, double* F, int mem
   job.consumer = 4;
   job.skm = to_dev(*model);
   const mag_stats keep = ctx->stats;  // the pass-1 timings stay the solve's
-  TRY(run_columns(ctx, job));
+  if (ctx->adj_kept) {
+    // the solve kept every column's pass-1 data: no second pass
+    TRY(adjoint_tail(ctx, job, ctx->k_cols.as<int32_t>(), ctx->adj_nu.as<int32_t>(), ctx->M, cap,
+                     device_count_cus(ctx->device)));
+  } else {
+    TRY(run_columns(ctx, job));
+  }
   ctx->stats.t_krylov_ms = keep.t_krylov_ms;
   ctx->stats.t_eig_ms = keep.t_eig_ms;
   ctx->stats.krylov_launches = keep.krylov_launches;
@@ -2041,7 +2071,9 @@ static int md_frame(mag_ctx* ctx, const mag_sk_model* model, const mag_opts* opt
   sys.r_cluster = md->r_cluster;
   TRY(mag_set_system(ctx, &sys, MAG_DEVICE));
   double mu = 0.0, E = 0.0, A = 0.0;
-  TRY(mag_solve_columns(ctx, opts, &mu, &E, &A));
+  mag_opts fo = *opts;
+  fo.keep_exact = md->exact_forces ? 1 : 0;  // the frame's exact gradient reuses pass 1
+  TRY(mag_solve_columns(ctx, &fo, &mu, &E, &A));
   if (md->exact_forces)
     TRY(mag_forces_exact(ctx, model, ctx->md_F.as<double>(), MAG_DEVICE));
   else
@@ -2157,7 +2189,7 @@ int mag_get_stats(mag_ctx* ctx, mag_stats* out) {
                           &ctx->md_sum, &ctx->f_part, &ctx->f_grad, &ctx->k_slots,
                           &ctx->k_qbeg, &ctx->adj_cvec, &ctx->adj_cdg, &ctx->adj_hbar,
                           &ctx->adj_wbar, &ctx->adj_fJ, &ctx->adj_F, &ctx->adj_counter,
-                          &ctx->adj_q, &ctx->adj_r, &ctx->adj_h, &ctx->adj_beta, &ctx->sk_cnt,
+                          &ctx->adj_q, &ctx->adj_r, &ctx->adj_h, &ctx->adj_beta, &ctx->adj_nu, &ctx->sk_cnt,
                           &ctx->sys_tmp, &ctx->sys_cnt, &ctx->sys_nz};
   for (const DevBuf* b : bufs) bytes += (int64_t)b->bytes;
   for (const CellList* c : {&ctx->sk_cells, &ctx->sys_cells})

@@ -373,6 +373,8 @@ struct mag_ctx {
   mag::DevBuf f_part, f_grad;  // force contraction: per-block parts, per-atom sums
   mag::DevBuf adj_cvec, adj_cdg, adj_hbar, adj_wbar, adj_fJ, adj_F, adj_counter;  // exact gradient
   mag::DevBuf adj_q, adj_r, adj_h, adj_beta;  // the forward pass's Krylov data for it
+  mag::DevBuf adj_nu;  // the kept pass's column dimensions
+  bool adj_kept = false;  // the last solve kept every column's exact-gradient inputs
   // set-up scratch kept between calls (an MD frame rebuilds pattern and clusters)
   mag::CellList sk_cells, sys_cells;
   mag::DevBuf sk_cnt, sys_tmp, sys_cnt, sys_nz;

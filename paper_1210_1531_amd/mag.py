@@ -40,7 +40,7 @@ def _is_dev(x):
 
 
 def make_opts(nu=30, kT=0.1, n_electrons=0.0, mu_tol=1e-12, mu_fixed=None, breakdown=1e-12,
-              workflow="auto", schedule="auto", eig_sweeps=0) -> L.MagOpts:
+              workflow="auto", schedule="auto", eig_sweeps=0, keep_exact=False) -> L.MagOpts:
     o = L.MagOpts()
     L.load().mag_opts_default(C.byref(o))
     o.nu = int(nu)
@@ -52,6 +52,7 @@ def make_opts(nu=30, kT=0.1, n_electrons=0.0, mu_tol=1e-12, mu_fixed=None, break
     o.workflow = _WORKFLOWS[workflow] if isinstance(workflow, str) else int(workflow)
     o.schedule = _SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.eig_sweeps = int(eig_sweeps)
+    o.keep_exact = int(bool(keep_exact))
     return o
 
 

@@ -110,3 +110,39 @@ def test_exact_forces_errors():
     with pytest.raises(MagError) as e:
         ctx.forces_exact(model.sk_model())  # nu above the kernel's capacity
     assert e.value.status == L.MAG_EUNSUPPORTED
+
+
+def test_kept_pass_gives_the_same_forces_and_goes_stale():
+    """keep_exact: the solve keeps every column's pass-1 data and
+    mag_forces_exact skips its own pass; the forces are bitwise those of the
+    second pass.  New values of H and S drop the kept data."""
+    import torch
+    import gen
+    from paper_1210_1531_amd import model
+    s = gen.make(2)
+    m = model.sk_model()
+    kw = dict(nu=s.nu, kT=s.kT, n_electrons=s.n_electrons)
+    ctx = gpu_context(s)
+    ctx.solve(**kw)
+    F_ref = np_(ctx.forces_exact(m))
+    t_ref = ctx.stats()["t_forces_exact_ms"]
+    ctx.solve(keep_exact=True, **kw)
+    F_kept = np_(ctx.forces_exact(m))
+    t_kept = ctx.stats()["t_forces_exact_ms"]
+    log(f"[exact kept] bitwise {np.array_equal(F_kept, F_ref)}; {t_ref:.1f} ms with the pass, "
+        f"{t_kept:.1f} ms from the kept data")
+    assert np.array_equal(F_kept, F_ref)
+    # the kept data belong to the old values: after an update the next solve
+    # (without keeping) and forces_exact use the new ones
+    pos1 = torch.tensor(s.pos + np.random.default_rng(3).normal(0.0, 0.01, s.pos.shape),
+                        dtype=torch.float64, device="cuda")
+    ctx.solve(keep_exact=True, **kw)
+    Hv, Sv = ctx.sk_values(pos1)
+    ctx.update_values(Hv, Sv)
+    ctx.solve(**kw)
+    F_new = np_(ctx.forces_exact(m))
+    fresh = gpu_context(s)
+    fresh.update_values(*fresh.sk_values(pos1))
+    fresh.solve(**kw)
+    assert np.array_equal(F_new, np_(fresh.forces_exact(m)))
+    assert not np.array_equal(F_new, F_ref)
