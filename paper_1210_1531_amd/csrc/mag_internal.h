@@ -38,6 +38,7 @@ enum KernelError : int {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  uint64_t epoch = 0;  // counts allocations: contents older than it are gone
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -58,6 +59,7 @@ struct DevBuf {
       return e;
     }
     bytes = n;
+    ++epoch;
     return hipSuccess;
   }
   template <typename T>
@@ -421,7 +423,27 @@ struct mag_ctx {
   mag::MuState h_state{};
 
   mag_stats stats{};
-  // per-launch timing events of the Krylov and eigensolver kernels (pass 1)
+  // per-launch timing events of the Krylov and eigensolver kernels (pass 1),
+  // read after the solve's one synchronisation
   std::vector<hipEvent_t> ev_pool;
   bool time_kernels = false;
+  size_t timed_launches = 0;
+  // stage timing events (start, end pairs), read after a synchronisation
+  std::vector<hipEvent_t> ev_span;
+  // pinned host memory that results are copied into in stream order, so
+  // that a call reads them after its one synchronisation: words 0-7 the
+  // kernel error flags, words 8-15 up to four doubles
+  int32_t* h_flags = nullptr;
+  bool pass2_pending = false;  // pass 2 enqueued, its flags not checked yet
+  // the launch lists of the last single-chunk pass over h_order, resident in
+  // k_slots and k_qbeg (valid while the system, nu capacity and buffers stay)
+  struct OrderLists {
+    bool valid = false;
+    uint64_t sys_gen = 0;
+    int cap = 0;
+    uint64_t slots_epoch = 0, qbeg_epoch = 0;
+    std::vector<int8_t> bucket;
+    std::vector<int32_t> hslots;
+    std::vector<int64_t> hqbeg, boff;
+  } lists;
 };
