@@ -33,6 +33,12 @@
  *     identical and include J itself.  Entry p of row r, column c of the
  *     density outputs holds rho_{c r} as obtained from column r, i.e. the
  *     coefficient of H_{r c} in E_band = sum_r sum_c H_{r c} rho_{c r}.
+ *   - Environment, read when a context first needs the value:
+ *     MAG_SCRATCH_GB (default 8) bounds the per-column scratch of one chunk
+ *     of columns; MAG_AUTOTUNE=0 keeps every Krylov launch plan at its
+ *     default instead of timing the candidates; MAG_LDS_CACHE=0 makes new
+ *     plans stream every matrix block instead of caching a cluster's first
+ *     blocks in LDS.  At nu <= 30 the last two change no result bit.
  */
 #ifndef MAG_H
 #define MAG_H

@@ -356,6 +356,19 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             MAG_BLOCK_FMA1
             ++e;
           }
+          // entries alternate between the two accumulator pairs by their
+          // offset in the row, so each pair sums the same blocks in the same
+          // order wherever the cached part ends (the result does not depend
+          // on the cache size of the launch plan): continue with the pair
+          // that the next offset's parity names, and swap after an odd
+          // number of entries
+          if ((e - e_beg[rr]) & 1) {
+            const double tw = wa, tz = za;
+            wa = wb;
+            za = zb;
+            wb = tw;
+            zb = tz;
+          }
           // streamed blocks, three per iteration (twelve loads in flight)
           const double* rp = rowp[rr];
           for (; e + 2 < e1; e += 3) {
@@ -381,6 +394,11 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
                 MAG_ROW_FMA(wa, za, h01[u], h23[u], s01[u], s23[u], x01, x23)
               }
             }
+            const double tw = wa, tz = za;  // three entries: the parity flips
+            wa = wb;
+            za = zb;
+            wb = tw;
+            zb = tz;
           }
           for (; e < e1; ++e) {
             const unsigned p0 = s_ent[e];
@@ -393,8 +411,13 @@ __global__ __launch_bounds__(KTPB) void krylov_kernel(KrylovArgs a) {
             const double2 x01 = *reinterpret_cast<const double2*>(s_x + k0);
             const double2 x23 = *reinterpret_cast<const double2*>(s_x + k0 + 2);
             MAG_ROW_FMA(wa, za, h01, h23, s01, s23, x01, x23)
+            const double tw = wa, tz = za;
+            wa = wb;
+            za = zb;
+            wb = tw;
+            zb = tz;
           }
-          w[rr] = wa + wb;
+          w[rr] = wa + wb;  // the same sum in either order
           z[rr] = za + zb;
         }
 
