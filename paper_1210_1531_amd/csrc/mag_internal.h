@@ -238,7 +238,11 @@ struct SKModelDev {
   double r0, r_on, r_cut;
 };
 // exact gradient of the truncated-Krylov grand potential (adjoint.hip)
-constexpr int ADJ_KC = 4;  // basis columns staged per contraction pass
+// basis columns staged per pass of the exact gradient's contraction: each
+// pass evaluates the pair derivatives of every cluster block once, so wider
+// passes evaluate them fewer times (ten: three passes at nu = 30, whose
+// kernel then holds 163,296 of the 163,840 bytes of LDS of a CU)
+constexpr int ADJ_KC = 10;
 struct AdjointArgs {
   const int32_t* bptr;
   const int32_t* bcol;
