@@ -285,6 +285,9 @@ __global__ __launch_bounds__(KTPB) void adjoint_kernel(AdjointArgs a) {
   const int tid = threadIdx.x;
   const int cap = a.cap;
   const Box box{{a.box[0], a.box[1], a.box[2]}};
+  // reciprocals for the contraction's minimum images and cutoff window
+  const double ibx = 1.0 / box.L[0], iby = 1.0 / box.L[1], ibz = 1.0 / box.L[2];
+  const double iw = 1.0 / (a.m.r_cut - a.m.r_on);
   // workgroup scratch: Wbar (then Z), Zs and Q, each NU columns of NROW rows
   double* wbar = a.wbar + (int64_t)blockIdx.x * 3 * NU * NROW;
   double* zsb = wbar + NU * NROW;
@@ -621,9 +624,11 @@ __global__ __launch_bounds__(KTPB) void adjoint_kernel(AdjointArgs a) {
                 for (int b = 0; b < 4; ++b) N[b] *= 2.0;
                 double dx = s_pos[3 * B] - s_pos[3 * A], dy = s_pos[3 * B + 1] - s_pos[3 * A + 1],
                        dz = s_pos[3 * B + 2] - s_pos[3 * A + 2];
-                min_image(box, dx, dy, dz);
+                dx -= box.L[0] * rint(dx * ibx);  // minimum image (|d| < r_cut < L / 2)
+                dy -= box.L[1] * rint(dy * iby);
+                dz -= box.L[2] * rint(dz * ibz);
                 double gp[3];
-                pair_row_grad(a.m, dx, dy, dz, ar, M, N, gp);
+                pair_row_grad(a.m, iw, dx, dy, dz, ar, M, N, gp);
                 g3[rr][0] += gp[0];
                 g3[rr][1] += gp[1];
                 g3[rr][2] += gp[2];

@@ -93,6 +93,27 @@ __device__ __forceinline__ void two_center_contract(const SKModelDev& m, const d
   }
 }
 
+// radial() from r and its reciprocal ri, with the reciprocal width iw of the
+// cutoff window: no division (the exact gradient evaluates it once per
+// cluster block, row and pass of its contraction)
+__device__ __forceinline__ void radial_ri(const SKModelDev& m, double r, double ri, double iw,
+                                          double& u, double& du) {
+  const double t = (r - m.r_on) * iw;
+  double fc = 1.0, dfc = 0.0;
+  if (t >= 1.0) {
+    fc = 0.0;
+  } else if (t > 0.0) {
+    const double t2 = t * t, t3 = t2 * t;
+    fc = 1.0 - (10.0 * t3 - 15.0 * t3 * t + 6.0 * t3 * t2);
+    dfc = -(30.0 * t2 - 60.0 * t3 + 30.0 * t3 * t) * iw;
+  }
+  const double q = m.r0 * ri;
+  const double g = q * q;
+  const double dg = -2.0 * g * ri;  // d/dr (r0 / r)^2
+  u = g * fc;
+  du = dg * fc + g * dfc;
+}
+
 // sum_b (Gh[b] dH_ab/dd + Gs[b] dS_ab/dd) for one row a of the pair's H and S
 // blocks (3-vector), with the weights of that row only.  Written out from the
 // two-center forms: with l = d / r, u(r), u'(r) and dl_b/dd_c = (delta_bc -
@@ -103,14 +124,16 @@ __device__ __forceinline__ void two_center_contract(const SKModelDev& m, const d
 //            + u' l (l_p (Q.l) + R_p),
 //            T0 = Gh0 Vsp + Gs0 Ssp, Q_b = Gh_{1+b} (Vpps - Vppp) + Gs_{1+b} (Spps - Sppp),
 //            R_p = Gh_{1+p} Vppp + Gs_{1+p} Sppp.
-__device__ __forceinline__ void pair_row_grad(const SKModelDev& m, double dx, double dy,
-                                              double dz, int a, const double Gh[4],
+// (iw: 1 / (r_cut - r_on); ri from the reciprocal square root, no division)
+__device__ __forceinline__ void pair_row_grad(const SKModelDev& m, double iw, double dx,
+                                              double dy, double dz, int a, const double Gh[4],
                                               const double Gs[4], double out[3]) {
-  const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  const double ri = 1.0 / r;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ri = rsqrt(r2);
+  const double r = r2 * ri;
   const double l[3] = {dx * ri, dy * ri, dz * ri};
   double u, du;
-  radial(m, r, u, du);
+  radial_ri(m, r, ri, iw, u, du);
   if (a == 0) {
     const double P0 = Gh[0] * m.vh[0] + Gs[0] * m.vs[0];
     double P[3], pl = 0.0;
