@@ -76,8 +76,9 @@ enum mag_mem { MAG_HOST = 0, MAG_DEVICE = 1 };
  * (eps, w) needed for mu and recomputes every Krylov column for rho in pass 2
  * (the letter's memory-saving workflow).  STORE: pass 1 also keeps Y d on the
  * pattern (n_pat x nu doubles per column) and pass 2 reads it back.  AUTO:
- * STORE when that buffer (nnz x nu doubles) fits in min(16 GB, a quarter of
- * the free device memory), RECOMPUTE otherwise. */
+ * STORE when that buffer (nnz x nu doubles) takes at most half of the free
+ * device memory (counting a buffer the context already holds for it),
+ * RECOMPUTE otherwise. */
 enum mag_workflow {
   MAG_WORKFLOW_RECOMPUTE = 0,
   MAG_WORKFLOW_STORE = 1,

@@ -1683,12 +1683,14 @@ int mag_solve_columns(mag_ctx* ctx, const mag_opts* opts, double* mu, double* E_
   if (opts->workflow == MAG_WORKFLOW_AUTO) {
     const double need = 8.0 * (double)ctx->nnz * opts->nu;
     const double held = ctx->P.p ? (double)ctx->P.bytes : 0.0;  // reusable
-    if (held >= need && need <= 16e9) {
+    if (held >= need) {
       ctx->opts.workflow = MAG_WORKFLOW_STORE;  // P is already there: no new memory
     } else {
+      // store when P takes at most half of the device memory that is free
+      // (or held by the P buffer it replaces)
       size_t free_b = 0, total_b = 0;
       if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-      const double limit = std::min(16e9, 0.25 * ((double)free_b + held));
+      const double limit = 0.5 * ((double)free_b + held);
       ctx->opts.workflow = need <= limit ? MAG_WORKFLOW_STORE : MAG_WORKFLOW_RECOMPUTE;
     }
   }
